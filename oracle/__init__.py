@@ -1,0 +1,13 @@
+"""CPU oracle for weighted betweenness centrality -- test infrastructure only.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never uses it.
+"""
+from .oracle import (  # noqa: F401
+    OracleError,
+    SigmaOverflow,
+    build,
+    oracle_bc,
+    oracle_source_state,
+    lib_path,
+)
