@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the weighted-betweenness hot path on one MI355X.
+
+Default workload: exact betweenness over all 100,000 sources of the
+Barabasi-Albert graph n = 100,000, 5 edges per new vertex (499,975 undirected
+edges), integer weights uniform in [1, 1000] (seeded, synthetic).  One step is
+one bc_compute over every source in the batched form (one persistent launch,
+one workgroup and one state slab per source in flight), inputs resident in
+HBM.  The plain form (one source at a time on the whole GPU) is timed on a
+source subset for comparison, and the CPU oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config ba100k]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+WORKLOADS = {
+    "ba100k": "Barabasi-Albert n=100000 m=5 (499975 edges), w uniform [1,1000], all 100000 sources",
+    "er1000": "Erdos-Renyi G(n=1000, M=4000), w uniform [1,100], all 1000 sources",
+    "grid1000": "1000x1000 4-neighbour grid minus 2% edges (1958040 edges), w uniform [1,255], "
+                "k=1024 sampled sources",
+    "rmat22": "directed R-MAT scale 22 (a,b,c=.57,.19,.19; self-loops/duplicates dropped), "
+              "w uniform [1,255], k=1024 sampled sources",
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def ensure_built():
+    lib = os.path.join(HERE, "paper_1701_05975_amd", "libbcgpu.so")
+    if not os.path.exists(lib):
+        from paper_1701_05975_amd import build
+        build.build()
+
+
+def cpu_baseline(g, sources, budget_sources: int, seed: int = 7):
+    """Oracle timed on a bounded sample of the same workload (host cores)."""
+    import oracle
+    if not os.path.exists(oracle.lib_path):
+        oracle.build()
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(np.asarray(sources), size=min(budget_sources, len(sources)),
+                                replace=False)).astype(np.int32)
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    oracle.oracle_bc(g, sample, threads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(len(sample) * g.m / dt / 1e9, 6),
+        "unit": "GTEPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{len(sample)} of the {len(sources)} sources (seed {seed}), "
+                  f"{dt:.2f} s wall on {threads} threads",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="ba100k", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-sources", type=int, default=64)
+    ap.add_argument("--cpu-sources", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--delta", type=int, default=0)
+    ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--lane-max", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--accumulate", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU form "
+              "(sources sharded over GPUs, one all-reduce of the centralities) is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    ensure_built()
+    import torch
+
+    from paper_1701_05975_amd import bc, graphgen as gg
+
+    t_gen = time.perf_counter()
+    g = gg.config_graph(args.config)
+    sources = gg.config_sources(args.config, g)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# graph {g.name}: n={g.n} m={g.m} nnz={g.nnz} k={len(sources)} "
+          f"(generated in {t_gen:.1f}s)", file=sys.stderr, flush=True)
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    G = bc.Graph(g)
+    src_dev = torch.from_numpy(sources).to("cuda")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    k = int(len(sources))
+
+    def opts(**kw):
+        base = dict(delta=args.delta, wg_threads=args.wg, lane_max_deg=args.lane_max,
+                    batch=args.batch, accumulate=args.accumulate,
+                    stream=stream.cuda_stream)
+        base.update(kw)
+        return bc.make_options(**base)
+
+    # warm-up (the first call autotunes and caches the settings on the graph)
+    o = opts(autotune=0 if args.no_autotune else 1)
+    for i in range(args.warmup):
+        st = bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
+        print(f"# warmup {i}: {st.ms:.1f} ms (delta={st.delta} wg={st.wg_threads} "
+              f"lane_max={st.lane_max_deg} batch={st.batch})", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        st = bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
+        stats.append(st)
+        print(f"# step {i}: {st.ms:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms_per_step = t / args.steps * 1e3
+    gteps = k * g.m * args.steps / t / 1e9
+    last = stats[-1]
+
+    kernel_ms = float(np.mean([s.kernel_ms for s in stats]))
+    achieved = last.algo_bytes / (kernel_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None,
+        "kernel": "k_batched",
+        "kernel_ms": round(kernel_ms, 3),
+        "algo_bytes_per_launch": last.algo_bytes,
+    }
+
+    plain = None
+    if not args.no_plain:
+        ps = sources[: min(args.plain_sources, k)]
+        ps_dev = torch.from_numpy(np.ascontiguousarray(ps)).to("cuda")
+        po = opts(mode=bc.BC_MODE_PLAIN)
+        bc.bc_compute_device(G.handle, ps_dev.data_ptr(), min(4, len(ps)), out.data_ptr(), po)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        pst = bc.bc_compute_device(G.handle, ps_dev.data_ptr(), len(ps), out.data_ptr(), po)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        plain = {"value": round(len(ps) * g.m / tp / 1e9, 6), "unit": "GTEPS",
+                 "sources": int(len(ps)), "ms": round(tp * 1e3, 2),
+                 "batched_over_plain": round(gteps / (len(ps) * g.m / tp / 1e9), 2)}
+
+    cpu = None if args.no_cpu else cpu_baseline(g, sources, args.cpu_sources)
+
+    rec = {
+        "metric": "weighted-BC GTEPS (sources x m / s), batched",
+        "value": round(gteps, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32/u64/f64",
+        "data": "synthetic (seeded generator, paper-style random weights)",
+        "config": {
+            "workload": f"{args.config}: {WORKLOADS[args.config]}",
+            "n": g.n, "m": g.m, "k": k,
+            "delta": last.delta, "wg_threads": last.wg_threads, "lane_max_deg": last.lane_max_deg,
+            "batch": last.batch, "accumulate": last.accumulate,
+            "reached": last.reached, "arcs_out_reached": last.arcs_out_reached,
+            "dag_arcs": last.dag_arcs, "improvements": last.improvements,
+            "bands": last.bands, "iterations": last.iterations,
+        },
+        "roofline": roofline,
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

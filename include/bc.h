@@ -1,0 +1,207 @@
+/*
+ * bc.h -- C ABI of the MI355X betweenness-centrality library.
+ *
+ * The library computes betweenness centrality on weighted graphs with
+ * Brandes' method as laid out by Fan, Xu & Zhao ("A GPU-Based Solution to
+ * Fast Calculation of Betweenness Centrality on Large Weighted Networks"):
+ * per source s, a weighted single-source shortest-path pass that records
+ * distances d(s,.) and shortest-path counts sigma_s(.) (Sec. 2.2, Sec. 3.1,
+ * Alg. 2), then a dependency pass in reverse distance order (Sec. 2.1 recursion,
+ * Alg. 3) whose values are added to the centrality of every vertex other
+ * than s.
+ *
+ *   BC_S(v) = sum over s in S, s != v, of delta_s(v)
+ *           = sum over s in S and t != s, v, of sigma_st(v) / sigma_st
+ *
+ * (Sec. 2.1, Eq. 1, restricted to a source multiset S; ordered pairs, no
+ * normalisation).  With S = all vertices this is Eq. 1 exactly.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a bc_status; no C++ exception crosses the ABI.  On
+ *     failure bc_last_error() describes the cause (thread-local string, valid
+ *     until the next call on the same thread).
+ *   - Out-parameters are written only when the call returns BC_OK.
+ *   - Host pointers are read during the call only and stay owned by the
+ *     caller.  Device pointers must point to memory of the current HIP
+ *     device, allocated by the caller, and stay owned by the caller.
+ *   - Handles (bc_graph, bc_result) are owned by the library and released
+ *     only by the matching destroy call.  A graph handle must not be used by
+ *     two threads at once.
+ *   - Numeric types: distances int32 (INT32_MAX marks "unreachable"),
+ *     path counts uint64 (an overflow is an error, never a wrap),
+ *     dependencies and centralities IEEE double.
+ */
+#ifndef BC_H
+#define BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BC_OK = 0,
+    BC_E_INVAL = 1,          /* bad argument: null pointer, negative size, source out of range */
+    BC_E_GRAPH = 2,          /* malformed CSR, or an undirected graph whose arcs are not symmetric */
+    BC_E_WEIGHT = 3,         /* an arc weight below 1 */
+    BC_E_DIST_OVERFLOW = 4,  /* (n-1) * max weight does not fit below INT32_MAX */
+    BC_E_SIGMA_OVERFLOW = 5, /* a shortest-path count exceeded 2^64 - 1 */
+    BC_E_NOMEM = 6,          /* device or host allocation failed */
+    BC_E_DEVICE = 7,         /* HIP runtime error, or no usable GPU */
+    BC_E_BUSY = 8,           /* request refused (server queue full / not admissible) */
+    BC_E_TIMEOUT = 9,        /* wait deadline passed */
+    BC_E_INTERNAL = 10       /* an internal safety bound tripped; results are not valid */
+} bc_status;
+
+/* bc_create_graph flags */
+#define BC_DIRECTED 1u /* arcs are one-way; without it every arc must have a reverse arc
+                          of equal weight (checked) */
+
+typedef struct bc_graph bc_graph;
+typedef struct bc_result bc_result;
+
+/*
+ * bc_create_graph -- copy a weighted graph to the device.
+ *
+ * The graph is given in CSR form plus a parallel weight array (Sec. 3.1):
+ * row_ptr[n+1] (int64, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ * col[nnz] (arc heads, 0 <= col < n) and w[nnz] (integer weights >= 1).
+ * Row v lists the arcs leaving v.  Without BC_DIRECTED the graph is
+ * undirected (Sec. 2.1): every arc (u, v, w) must have the reverse arc
+ * (v, u, w), which is verified.  Parallel arcs are distinct paths; self-loops
+ * are allowed and never lie on a shortest path.
+ *
+ * Errors: BC_E_INVAL (n < 1, nnz < 0, null pointer, nnz >= 2^32 - 1),
+ * BC_E_GRAPH, BC_E_WEIGHT, BC_E_DIST_OVERFLOW, BC_E_NOMEM, BC_E_DEVICE.
+ * The host arrays are copied; *out receives a new handle.
+ */
+bc_status bc_create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                          const int32_t *w, uint32_t flags, bc_graph **out);
+
+/* Release a graph and every device buffer cached on it.  NULL is accepted. */
+bc_status bc_destroy_graph(bc_graph *g);
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int32_t directed;
+    int32_t w_max;
+    int32_t max_out_degree;
+    int32_t packed_arcs; /* 1 when arc head and weight share one 32-bit word on the device */
+    int64_t device_bytes; /* graph bytes resident on the device */
+} bc_graph_info;
+
+bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info);
+
+/* Execution forms. */
+typedef enum {
+    BC_MODE_AUTO = 0,    /* batched */
+    BC_MODE_BATCHED = 1, /* many sources in flight, one workgroup and one state slab per source,
+                            one persistent launch (coarse-grained source parallelism, Sec. 3.1) */
+    BC_MODE_PLAIN = 2    /* one source at a time on the whole GPU, phase by phase */
+} bc_mode;
+
+/*
+ * Options.  A zero field selects the default (or the autotuned value when
+ * autotune is set).  The result never depends on the options beyond
+ * floating-point summation order.
+ */
+typedef struct {
+    int32_t mode;         /* bc_mode */
+    int32_t batch;        /* batched: sources in flight (state slabs); 0 = fill the GPU */
+    int32_t delta;        /* near-far band width in weight units (>= 1); 0 = heuristic */
+    int32_t lane_max_deg; /* vertices with at most this many arcs are scanned by one lane,
+                             larger ones by a whole 64-lane wave */
+    int32_t wg_threads;   /* batched: threads per workgroup (256, 512 or 1024) */
+    int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best */
+    int32_t accumulate;   /* 0 = default, 1 = per-slot partial sums + reduction,
+                             2 = device-wide FP64 atomic adds into the output */
+    int32_t reserved;
+    void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
+} bc_options;
+
+typedef struct {
+    double ms;                /* device time of the computation (HIP events) */
+    int64_t sources;          /* k */
+    int64_t reached;          /* sum over sources of reached vertices (n_R) */
+    int64_t arcs_out_reached; /* sum over sources of arcs leaving reached vertices (A_R) */
+    int64_t dag_arcs;         /* sum over sources of shortest-path DAG arcs (E_D) */
+    int64_t improvements;     /* successful distance decreases (relaxation work) */
+    int64_t bands;            /* near-far bands (distance buckets) */
+    int64_t iterations;       /* frontier expansion steps */
+    int64_t sigma_rounds;     /* path-count rounds over band members */
+    int64_t delta_rounds;     /* dependency rounds over band members */
+    int64_t first_bad_source; /* smallest source-list index whose counts overflowed, else -1 */
+    double algo_bytes;        /* algorithmic bytes of the work (see bc_algo_bytes) */
+    double kernel_ms;         /* device time of the main kernel launches alone (HIP events) */
+    int64_t kernel_launches;  /* number of main kernel launches timed in kernel_ms */
+    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate;
+} bc_stats;
+
+/*
+ * bc_compute -- betweenness over a multiset of sources.
+ *
+ * sources[k] (host, int32) lists the sources; NULL with k = n means all
+ * vertices 0..n-1 (exact Eq. 1).  Repeated sources count once per
+ * occurrence; k = 0 gives an all-zero result.  The result is the unscaled
+ * sum of the listed sources' dependencies.  Runs on opt->stream (or the
+ * graph's stream) and returns after the result is complete.
+ *
+ * Errors: BC_E_INVAL (source out of range, k < 0), BC_E_SIGMA_OVERFLOW (the
+ * result handle is still not produced; bc_last_error names the first
+ * failing source index), BC_E_NOMEM, BC_E_DEVICE, BC_E_INTERNAL.
+ */
+bc_status bc_compute(bc_graph *g, const int32_t *sources, int64_t k, const bc_options *opt,
+                     bc_result **out);
+
+/*
+ * bc_compute_device -- as bc_compute, for data already on the device.
+ *
+ * sources_dev[k] is a device int32 array; bc_dev[n] is a device double array
+ * that receives the result (overwritten).  The call enqueues the work on
+ * opt->stream (or the graph's stream) and waits for it; stats may be NULL.
+ * No host<->device transfer of inputs or outputs takes place.
+ */
+bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
+                            const bc_options *opt, double *bc_dev, bc_stats *stats);
+
+/* Copy a result's centralities to host memory bc_host[n]. */
+bc_status bc_result_bc(const bc_result *r, double *bc_host);
+/* Device pointer to a result's centralities (double[n], owned by the result). */
+bc_status bc_result_device_ptr(const bc_result *r, const double **bc_dev);
+bc_status bc_result_stats(const bc_result *r, bc_stats *stats);
+bc_status bc_destroy_result(bc_result *r);
+
+/*
+ * bc_source_state -- full per-vertex state of one source, for checking.
+ *
+ * Runs source s alone with the given options and copies to host arrays of n
+ * elements: d (INT32_MAX when unreachable), sigma (0 when unreachable) and
+ * delta (dependency delta_s(v); 0 when unreachable; delta_s(s) equals the
+ * number of reached vertices minus one).  Any output pointer may be NULL.
+ */
+bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t *d,
+                          uint64_t *sigma, double *delta);
+
+/*
+ * bc_algo_bytes -- the algorithmic HBM bytes of one source's Brandes pass:
+ *   arcs * (16 + 2 * weight_bytes) + 72 * reached + 24 * dag_arcs + 20 * n
+ * (two passes over the arcs of reached vertices with a 4-byte distance gather
+ * each, per-vertex state reads and writes, the count and dependency gathers
+ * along shortest-path DAG arcs, and the per-source initialisation).
+ */
+double bc_algo_bytes(int32_t n, int32_t weight_bytes, int64_t arcs, int64_t reached,
+                     int64_t dag_arcs);
+
+const char *bc_last_error(void);
+
+/* Library version string. */
+const char *bc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H */

@@ -1,0 +1,100 @@
+// autotune.cpp -- per-graph search over the batched form's settings.
+//
+// Coordinate descent over the near-far band width, the workgroup size, the
+// lane/wave degree threshold and the number of sources in flight, each
+// candidate timed on a prefix of the caller's source list.  The winner is
+// cached on the graph handle and reused by later calls.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "bc_internal.h"
+
+static double time_candidate(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev,
+                             int64_t k, double *scratch)
+{
+    DevCounters cnt;
+    float ms = 0.f;
+    run_batched(g, r, src_dev, k, scratch, cnt, ms, nullptr);
+    if (cnt.err[0])
+        return 1e30; // a setting that trips a bound is never chosen
+    return (double)ms;
+}
+
+void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int32_t *src_dev,
+              int64_t k)
+{
+    bc_options o;
+    memset(&o, 0, sizeof o);
+    if (opt)
+        o = *opt;
+    if (!g->tuned.valid) {
+        const int fill = r.batch;
+        int64_t sample = std::min<int64_t>(k, std::max<int64_t>(2 * (int64_t)fill, 64));
+        DevBuf scratch;
+        scratch.alloc((size_t)g->n * sizeof(double));
+        ResolvedOptions c = r;
+        c.batch = (int)std::min<int64_t>(fill, sample);
+        // warm-up: allocates the slabs and faults in the graph
+        time_candidate(g, c, src_dev, sample, (double *)scratch.p);
+        double best = time_candidate(g, c, src_dev, sample, (double *)scratch.p);
+
+        if (!o.delta) {
+            const int d0 = c.delta;
+            for (double f : {0.125, 0.25, 0.5, 2.0, 4.0, 8.0}) {
+                ResolvedOptions t = c;
+                t.delta = std::max(1, (int)(d0 * f));
+                const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
+                if (ms < best) {
+                    best = ms;
+                    c = t;
+                }
+            }
+        }
+        if (!o.wg_threads) {
+            for (int nt : {256, 512, 1024}) {
+                if (nt == c.wg_threads)
+                    continue;
+                ResolvedOptions t = c;
+                t.wg_threads = nt;
+                t.batch = std::max(1, (int)std::min<int64_t>(
+                                          (int64_t)g->num_cus *
+                                              batched_occupancy(g, nt, t.accumulate == 2),
+                                          sample));
+                const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
+                if (ms < best) {
+                    best = ms;
+                    c = t;
+                }
+            }
+        }
+        if (!o.lane_max_deg) {
+            for (int lm : {4, 8, 16, 64, 128}) {
+                ResolvedOptions t = c;
+                t.lane_max = lm;
+                const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
+                if (ms < best) {
+                    best = ms;
+                    c = t;
+                }
+            }
+        }
+        g->tuned.valid = true;
+        g->tuned.delta = c.delta;
+        g->tuned.lane_max = c.lane_max;
+        g->tuned.wg_threads = c.wg_threads;
+        g->tuned.best_ms_per_source = best / (double)sample;
+    }
+    if (!o.delta)
+        r.delta = g->tuned.delta;
+    if (!o.lane_max_deg)
+        r.lane_max = g->tuned.lane_max;
+    if (!o.wg_threads && r.wg_threads != g->tuned.wg_threads) {
+        r.wg_threads = g->tuned.wg_threads;
+        if (!o.batch)
+            r.batch = std::max(1, (int)std::min<int64_t>(
+                                      (int64_t)g->num_cus *
+                                          batched_occupancy(g, r.wg_threads, r.accumulate == 2),
+                                      k));
+    }
+}

@@ -1,0 +1,811 @@
+// bc_api.cpp -- host runtime behind the C ABI declared in include/bc.h.
+//
+// Graph ingest (CSR validation, symmetric check, transpose for directed
+// graphs, arc packing, upload), per-graph workspaces (state slabs, counters),
+// the batched and plain drivers, results and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+#include "bc_internal.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+bc_error::bc_error(bc_status s, const char *fmt, ...) : status(s)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    msg = buf;
+}
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return;
+    bc_status s = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BC_E_NOMEM
+                                                                               : BC_E_DEVICE;
+    (void)hipGetLastError(); // clear the non-sticky error state
+    throw bc_error(s, "%s: %s", what, hipGetErrorString(e));
+}
+
+bc_status bc_fail(const bc_error &e)
+{
+    g_last_error = e.msg;
+    return e.status;
+}
+
+template <class F> static bc_status guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return BC_OK;
+    } catch (const bc_error &e) {
+        return bc_fail(e);
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return BC_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return BC_E_INTERNAL;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return BC_E_INTERNAL;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+void DevBuf::alloc(size_t n)
+{
+    release();
+    if (n == 0)
+        return;
+    hip_check(hipMalloc(&p, n), "hipMalloc");
+    bytes = n;
+}
+
+void DevBuf::release()
+{
+    if (p)
+        (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+static void ensure_device()
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        throw bc_error(BC_E_DEVICE, "no HIP device available");
+    }
+}
+
+static int bit_width_u64(uint64_t x)
+{
+    int b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Graph ingest
+// ---------------------------------------------------------------------------
+static void build_transpose(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                            const int32_t *w, std::vector<int64_t> &trow,
+                            std::vector<int32_t> &tcol, std::vector<int32_t> &tw)
+{
+    const int64_t nnz = row_ptr[n];
+    trow.assign((size_t)n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e)
+        trow[(size_t)col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v)
+        trow[(size_t)v + 1] += trow[(size_t)v];
+    std::vector<int64_t> pos(trow.begin(), trow.end() - 1);
+    tcol.resize((size_t)nnz);
+    tw.resize((size_t)nnz);
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int64_t p = pos[(size_t)col[e]]++;
+            tcol[(size_t)p] = u;
+            tw[(size_t)p] = w[e];
+        }
+}
+
+// Undirected input must list every edge in both directions with one weight:
+// row v of the graph and row v of its transpose must be equal multisets.
+static bool rows_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                           const int32_t *w, const std::vector<int64_t> &trow,
+                           const std::vector<int32_t> &tcol, const std::vector<int32_t> &tw)
+{
+    std::vector<uint64_t> a, b;
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t b0 = row_ptr[v], b1 = row_ptr[v + 1];
+        const int64_t t0 = trow[(size_t)v], t1 = trow[(size_t)v + 1];
+        if (b1 - b0 != t1 - t0)
+            return false;
+        a.clear();
+        b.clear();
+        for (int64_t e = b0; e < b1; ++e)
+            a.push_back(((uint64_t)(uint32_t)col[e] << 32) | (uint32_t)w[e]);
+        for (int64_t e = t0; e < t1; ++e)
+            b.push_back(((uint64_t)(uint32_t)tcol[(size_t)e] << 32) | (uint32_t)tw[(size_t)e]);
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a != b)
+            return false;
+    }
+    return true;
+}
+
+static void upload_arcs(bc_graph *g, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                        const int32_t *w, DevBuf &drow, DevBuf &darc, DevBuf &dwt)
+{
+    const int64_t nnz = row_ptr[n];
+    std::vector<uint32_t> r((size_t)n + 1);
+    for (int32_t v = 0; v <= n; ++v)
+        r[(size_t)v] = (uint32_t)row_ptr[v];
+    std::vector<uint32_t> a((size_t)nnz);
+    if (g->packed) {
+        for (int64_t e = 0; e < nnz; ++e)
+            a[(size_t)e] = ((uint32_t)col[e] << g->wshift) | ((uint32_t)(w[e] - 1) & g->wmask);
+    } else {
+        for (int64_t e = 0; e < nnz; ++e)
+            a[(size_t)e] = (uint32_t)col[e];
+    }
+    drow.alloc(r.size() * sizeof(uint32_t));
+    hip_check(hipMemcpy(drow.p, r.data(), r.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+              "upload row offsets");
+    if (nnz > 0) {
+        darc.alloc(a.size() * sizeof(uint32_t));
+        hip_check(hipMemcpy(darc.p, a.data(), a.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                  "upload arcs");
+        if (!g->packed) {
+            dwt.alloc((size_t)nnz * sizeof(int32_t));
+            hip_check(hipMemcpy(dwt.p, w, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice),
+                      "upload weights");
+        }
+    }
+}
+
+static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *w, uint32_t flags, bc_graph **out)
+{
+    if (!out)
+        throw bc_error(BC_E_INVAL, "out is NULL");
+    if (n < 1)
+        throw bc_error(BC_E_INVAL, "n must be >= 1 (got %d)", n);
+    if (nnz < 0)
+        throw bc_error(BC_E_INVAL, "nnz must be >= 0");
+    if (nnz >= (int64_t)UINT32_MAX)
+        throw bc_error(BC_E_INVAL, "nnz must be below 2^32 - 1");
+    if (!row_ptr || (nnz > 0 && (!col || !w)))
+        throw bc_error(BC_E_INVAL, "null CSR array");
+    if (flags & ~BC_DIRECTED)
+        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~BC_DIRECTED);
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz)
+        throw bc_error(BC_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    int64_t maxdeg = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t dg = row_ptr[v + 1] - row_ptr[v];
+        if (dg < 0)
+            throw bc_error(BC_E_GRAPH, "row_ptr decreases at row %d", v);
+        maxdeg = std::max(maxdeg, dg);
+    }
+    int32_t wmax = 1;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (col[e] < 0 || col[e] >= n)
+            throw bc_error(BC_E_GRAPH, "col[%lld] = %d out of range", (long long)e, col[e]);
+        if (w[e] < 1)
+            throw bc_error(BC_E_WEIGHT, "w[%lld] = %d is below 1", (long long)e, w[e]);
+        wmax = std::max(wmax, w[e]);
+    }
+    if ((int64_t)(n - 1) * (int64_t)wmax > (int64_t)INT32_MAX - 1)
+        throw bc_error(BC_E_DIST_OVERFLOW, "(n-1)*max weight = %lld does not fit in int32",
+                       (long long)(n - 1) * wmax);
+    const bool directed = (flags & BC_DIRECTED) != 0;
+
+    std::vector<int64_t> trow;
+    std::vector<int32_t> tcol, tw;
+    build_transpose(n, row_ptr, col, w, trow, tcol, tw);
+    if (!directed && !rows_symmetric(n, row_ptr, col, w, trow, tcol, tw))
+        throw bc_error(BC_E_GRAPH,
+                       "undirected graph is not symmetric (every arc needs a reverse arc of "
+                       "equal weight); pass BC_DIRECTED for one-way arcs");
+
+    ensure_device();
+    std::unique_ptr<bc_graph> g(new bc_graph());
+    g->n = n;
+    g->nnz = nnz;
+    g->directed = directed;
+    g->wmax = wmax;
+    g->maxdeg = (int32_t)std::min<int64_t>(maxdeg, INT32_MAX);
+    const int colbits = bit_width_u64((uint64_t)(n - 1));
+    const int wbits = bit_width_u64((uint64_t)(wmax - 1));
+    g->packed = colbits + wbits <= 32 && wbits < 32;
+    g->wshift = g->packed ? (uint32_t)wbits : 0u;
+    g->wmask = g->packed ? (wbits == 0 ? 0u : (uint32_t)((1ull << wbits) - 1)) : 0u;
+    g->wbytes = wmax <= 255 ? 1 : (wmax <= 65535 ? 2 : 4);
+    int64_t nz_rows = 0;
+    for (int32_t v = 0; v < n; ++v)
+        nz_rows += row_ptr[v + 1] > row_ptr[v];
+    g->avg_deg = nz_rows ? (double)nnz / (double)nz_rows : 0.0;
+    double wsum = 0;
+    for (int64_t e = 0; e < nnz; ++e)
+        wsum += w[e];
+    g->wmean = nnz ? wsum / (double)nnz : 1.0;
+
+    hip_check(hipGetDevice(&g->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, g->device), "hipGetDeviceProperties");
+    g->num_cus = prop.multiProcessorCount;
+    hip_check(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreate(&g->ev_k0), "hipEventCreate");
+    hip_check(hipEventCreate(&g->ev_k1), "hipEventCreate");
+
+    upload_arcs(g.get(), n, row_ptr, col, w, g->row, g->arc, g->wt);
+    if (directed) {
+        upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc, g->twt);
+    }
+    g->dnode.alloc((size_t)n * sizeof(int32_t));
+    g->deg.alloc((size_t)n * sizeof(int32_t));
+    hip_check(launch_graph_vertex_info(g->view(), g->packed, (int32_t *)g->dnode.p,
+                                       (int32_t *)g->deg.p, g->stream),
+              "vertex info");
+    g->ctl.alloc(sizeof(DevCounters));
+    g->plain_ctl.alloc(sizeof(PlainCtl));
+    hip_check(hipHostMalloc((void **)&g->host_counters, sizeof(DevCounters)), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&g->host_plain, sizeof(PlainCtl)), "hipHostMalloc");
+    hip_check(hipStreamSynchronize(g->stream), "graph upload");
+    *out = g.release();
+}
+
+DevGraph bc_graph::view() const
+{
+    DevGraph d;
+    d.row = (const uint32_t *)row.p;
+    d.arc = (const uint32_t *)arc.p;
+    d.wt = (const int32_t *)wt.p;
+    if (directed) {
+        d.trow = (const uint32_t *)trow.p;
+        d.tarc = (const uint32_t *)tarc.p;
+        d.twt = (const int32_t *)twt.p;
+    } else {
+        d.trow = d.row;
+        d.tarc = d.arc;
+        d.twt = d.wt;
+    }
+    d.n = n;
+    d.wshift = wshift;
+    d.wmask = wmask;
+    return d;
+}
+
+bc_graph::~bc_graph()
+{
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+    if (ev_k0)
+        (void)hipEventDestroy(ev_k0);
+    if (ev_k1)
+        (void)hipEventDestroy(ev_k1);
+    if (host_counters)
+        (void)hipHostFree(host_counters);
+    if (host_plain)
+        (void)hipHostFree(host_plain);
+}
+
+// ---------------------------------------------------------------------------
+// Workspaces
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SlabLayout slab_layout(int32_t n)
+{
+    SlabLayout L;
+    const size_t nn = (size_t)n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.d = take(4 * nn);
+    L.sigma = take(8 * nn);
+    L.delta = take(8 * nn);
+    L.bcp = take(8 * nn);
+    L.stamp = take(4 * nn);
+    L.infar = take(4 * nn);
+    L.order = take(4 * nn);
+    L.qa = take(4 * nn);
+    L.qb = take(4 * nn);
+    L.fa = take(4 * nn);
+    L.fb = take(4 * nn);
+    L.band_off = take(4 * (nn + 2));
+    L.hdr = take(64);
+    L.stride = o;
+    return L;
+}
+
+static void ensure_slabs(bc_graph *g, Workspace &ws, int nslabs, hipStream_t st)
+{
+    if (ws.base.p && ws.nslabs >= nslabs)
+        return;
+    ws.base.release();
+    ws.L = slab_layout(g->n);
+    const size_t bytes = ws.L.stride * (size_t)nslabs;
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if (bytes > free_b)
+        throw bc_error(BC_E_NOMEM, "state slabs need %zu bytes, %zu free", bytes, free_b);
+    ws.base.alloc(bytes);
+    ws.nslabs = nslabs;
+    hip_check(launch_slab_reset((char *)ws.base.p, ws.L, nslabs, g->n, st), "slab reset");
+}
+
+static void ensure_sources(bc_graph *g, int64_t k)
+{
+    const size_t need = (size_t)std::max<int64_t>(k, 1) * sizeof(int32_t);
+    if (g->src_buf.bytes < need)
+        g->src_buf.alloc(need);
+}
+
+// ---------------------------------------------------------------------------
+// Options
+// ---------------------------------------------------------------------------
+int default_delta(const bc_graph *g)
+{
+    // Band width of the near-far split: a few mean arc weights per average
+    // degree (tuned per graph by the autotuner when asked).
+    const double avg = std::max(1.0, g->avg_deg);
+    double d = 4.0 * (double)g->wmax / avg;
+    d = std::max(d, 1.0);
+    d = std::min(d, (double)INT32_MAX / 4);
+    return (int)d;
+}
+
+int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc)
+{
+    return batched_blocks_per_cu(g->packed, nt, atomic_bc);
+}
+
+ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
+{
+    ResolvedOptions r;
+    bc_options o;
+    memset(&o, 0, sizeof o);
+    if (opt)
+        o = *opt;
+    if (o.mode < 0 || o.mode > BC_MODE_PLAIN)
+        throw bc_error(BC_E_INVAL, "unknown mode %d", o.mode);
+    if (o.batch < 0 || o.delta < 0 || o.lane_max_deg < 0 || o.wg_threads < 0)
+        throw bc_error(BC_E_INVAL, "negative option");
+    if (o.accumulate < 0 || o.accumulate > 2)
+        throw bc_error(BC_E_INVAL, "unknown accumulate mode %d", o.accumulate);
+    r.mode = o.mode == BC_MODE_PLAIN ? BC_MODE_PLAIN : BC_MODE_BATCHED;
+    r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
+    r.wg_threads = o.wg_threads ? o.wg_threads : 256;
+    if (r.wg_threads != 256 && r.wg_threads != 512 && r.wg_threads != 1024)
+        throw bc_error(BC_E_INVAL, "wg_threads must be 256, 512 or 1024");
+    r.delta = o.delta ? o.delta : default_delta(g);
+    r.lane_max = o.lane_max_deg ? o.lane_max_deg : 32;
+    r.accumulate = o.accumulate ? o.accumulate : 1;
+    const int fill = g->num_cus * batched_occupancy(g, r.wg_threads, r.accumulate == 2);
+    int64_t b = o.batch ? o.batch : fill;
+    b = std::min<int64_t>(b, std::max<int64_t>(k, 1));
+    // keep the slabs within half of the free device memory
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const size_t stride = slab_layout(g->n).stride;
+    const size_t have = g->batched.base.p ? (size_t)g->batched.nslabs * stride : 0;
+    const int64_t by_mem = (int64_t)((free_b + have) / 2 / std::max<size_t>(stride, 1));
+    if (by_mem < 1)
+        throw bc_error(BC_E_NOMEM, "one state slab (%zu bytes) does not fit", stride);
+    b = std::min<int64_t>(b, by_mem);
+    b = std::min<int64_t>(b, 65535);
+    r.batch = (int)std::max<int64_t>(b, 1);
+    r.autotune = o.autotune;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Drivers
+// ---------------------------------------------------------------------------
+static void reset_counters(bc_graph *g, hipStream_t st)
+{
+    DevCounters *c = (DevCounters *)g->ctl.p;
+    hip_check(launch_fill_u64((unsigned long long *)c, sizeof(DevCounters) / 8, 0ull, st),
+              "reset counters");
+    hip_check(launch_fill_u64(&c->err[1], 1, (unsigned long long)INT64_MAX, st), "reset");
+}
+
+static void read_counters(bc_graph *g, hipStream_t st, DevCounters &out)
+{
+    hip_check(hipMemcpyAsync(g->host_counters, g->ctl.p, sizeof(DevCounters),
+                             hipMemcpyDeviceToHost, st),
+              "read counters");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    out = *g->host_counters;
+}
+
+static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters &c, int64_t k,
+                       double ms, double kernel_ms, int64_t launches, bc_stats *st)
+{
+    if (!st)
+        return;
+    memset(st, 0, sizeof *st);
+    st->ms = ms;
+    st->kernel_ms = kernel_ms;
+    st->kernel_launches = launches;
+    st->sources = k;
+    st->reached = (int64_t)c.stats.reached;
+    st->arcs_out_reached = (int64_t)c.stats.arcs;
+    st->dag_arcs = (int64_t)c.stats.dag;
+    st->improvements = (int64_t)c.stats.improvements;
+    st->bands = (int64_t)c.stats.bands;
+    st->iterations = (int64_t)c.stats.iterations;
+    st->sigma_rounds = (int64_t)c.stats.sigma_rounds;
+    st->delta_rounds = (int64_t)c.stats.delta_rounds;
+    st->first_bad_source = (c.err[0] & BC_ERRBIT_SIGMA) ? (int64_t)c.err[1] : -1;
+    // Per-source byte model summed over sources: the n-dependent term once per source.
+    st->algo_bytes = (double)k * 20.0 * (double)g->n +
+                     (double)st->arcs_out_reached * (16.0 + 2.0 * g->wbytes) +
+                     72.0 * (double)st->reached + 24.0 * (double)st->dag_arcs;
+    st->mode = r.mode;
+    st->batch = r.batch;
+    st->delta = r.delta;
+    st->lane_max_deg = r.lane_max;
+    st->wg_threads = r.wg_threads;
+    st->accumulate = r.accumulate;
+}
+
+static void check_device_errors(const DevCounters &c)
+{
+    if (c.err[0] & BC_ERRBIT_INTERNAL)
+        throw bc_error(BC_E_INTERNAL, "an internal iteration bound tripped; result invalid");
+    if (c.err[0] & BC_ERRBIT_SIGMA)
+        throw bc_error(BC_E_SIGMA_OVERFLOW,
+                       "shortest-path count exceeded 2^64-1 (first source-list index %lld)",
+                       (long long)c.err[1]);
+}
+
+void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
+                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms)
+{
+    hipStream_t st = r.stream;
+    ensure_slabs(g, g->batched, r.batch, st);
+    reset_counters(g, st);
+    const bool atomic_bc = r.accumulate == 2;
+    if (atomic_bc || k == 0)
+        hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    hip_check(hipEventRecord(e0, st), "event");
+    if (k > 0) {
+        BatchArgs a;
+        a.g = g->view();
+        a.slab_base = (char *)g->batched.base.p;
+        a.L = g->batched.L;
+        a.sources = src_dev;
+        a.k = k;
+        DevCounters *c = (DevCounters *)g->ctl.p;
+        a.next_src = &c->next_src;
+        a.bc_out = bc_dev;
+        a.delta = (uint32_t)r.delta;
+        a.lane_max = r.lane_max;
+        a.stats = &c->stats;
+        a.err = c->err;
+        const int nslabs = (int)std::min<int64_t>(r.batch, k);
+        hip_check(hipEventRecord(g->ev_k0, st), "event");
+        hip_check(launch_batched(a, g->packed, r.wg_threads, atomic_bc, nslabs, st),
+                  "batched kernel");
+        hip_check(hipEventRecord(g->ev_k1, st), "event");
+        if (!atomic_bc)
+            hip_check(launch_reduce_partials(a.slab_base, a.L, nslabs, g->n, bc_dev, st),
+                      "reduce");
+    }
+    hip_check(hipEventRecord(e1, st), "event");
+    read_counters(g, st, cnt);
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+    if (kernel_ms) {
+        *kernel_ms = 0.f;
+        if (k > 0)
+            hip_check(hipEventElapsedTime(kernel_ms, g->ev_k0, g->ev_k1), "event time");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_host, int64_t k,
+                      double *bc_dev, DevCounters &cnt, float &ms)
+{
+    hipStream_t st = r.stream;
+    ensure_slabs(g, g->plain, 1, st);
+    reset_counters(g, st);
+    hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
+    PlainArgs a;
+    a.g = g->view();
+    a.slab_base = (char *)g->plain.base.p;
+    a.L = g->plain.L;
+    a.ctl = (PlainCtl *)g->plain_ctl.p;
+    a.bc_out = bc_dev;
+    a.delta = (uint32_t)r.delta;
+    a.lane_max = r.lane_max;
+    DevCounters *c = (DevCounters *)g->ctl.p;
+    a.stats = &c->stats;
+    a.err = c->err;
+    const int grid = g->num_cus * 4;
+    if (!g->plain_ctl_ready) {
+        PlainCtl init;
+        memset(&init, 0, sizeof init);
+        init.phase = 4;
+        hip_check(hipMemcpyAsync(a.ctl, &init, sizeof init, hipMemcpyHostToDevice, st), "ctl");
+        hip_check(hipStreamSynchronize(st), "ctl");
+        g->plain_ctl_ready = true;
+    }
+    const unsigned long long iter_cap = 8ull * (unsigned long long)g->n + 1024ull;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    hip_check(hipEventRecord(e0, st), "event");
+    for (int64_t i = 0; i < k; ++i) {
+        const bool clear = g->plain_gen_hint > (1 << 30);
+        if (clear)
+            g->plain_gen_hint = 0;
+        hip_check(launch_plain_source(a, g->packed, grid, src_host[i], (long long)i, clear, st),
+                  "plain setup");
+        // set the iteration bound (host-side value, copied once per source)
+        hip_check(launch_fill_u64(&a.ctl->iter_cap, 1, iter_cap, st), "cap");
+        int pairs = 8;
+        long long total_pairs = 0;
+        for (;;) {
+            hip_check(launch_plain_steps(a, g->packed, grid, pairs, st), "plain steps");
+            total_pairs += pairs;
+            hip_check(hipMemcpyAsync(g->host_plain, a.ctl, sizeof(PlainCtl),
+                                     hipMemcpyDeviceToHost, st),
+                      "read phase");
+            hip_check(hipStreamSynchronize(st), "synchronize");
+            if (g->host_plain->phase == 4)
+                break;
+            if (total_pairs > 64ll * (long long)iter_cap + 4096)
+                throw bc_error(BC_E_INTERNAL, "plain phase machine did not finish");
+            pairs = std::min(pairs * 2, 256);
+        }
+        g->plain_gen_hint = g->host_plain->gen;
+        if (g->host_plain->abort)
+            hip_check(launch_plain_clear_infar(a, st), "clear");
+    }
+    hip_check(hipEventRecord(e1, st), "event");
+    read_counters(g, st, cnt);
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
+                    const bc_options *opt, double *bc_dev, bc_stats *stats)
+{
+    ResolvedOptions r = resolve_options(g, opt, k);
+    if (r.autotune && r.mode == BC_MODE_BATCHED && k > 0)
+        autotune(g, r, opt, src_dev, k);
+    DevCounters cnt;
+    float ms = 0.f, kms = 0.f;
+    int64_t launches = 0;
+    if (r.mode == BC_MODE_PLAIN) {
+        std::vector<int32_t> hs;
+        if (!src_host && k > 0) {
+            hs.resize((size_t)k);
+            hip_check(hipMemcpyAsync(hs.data(), src_dev, (size_t)k * 4, hipMemcpyDeviceToHost,
+                                     r.stream),
+                      "sources to host");
+            hip_check(hipStreamSynchronize(r.stream), "synchronize");
+            for (int64_t i = 0; i < k; ++i)
+                if (hs[(size_t)i] < 0 || hs[(size_t)i] >= g->n)
+                    throw bc_error(BC_E_INVAL, "source %d out of range", hs[(size_t)i]);
+            src_host = hs.data();
+        }
+        run_plain(g, r, src_host, k, bc_dev, cnt, ms);
+        kms = ms;
+        launches = 0;
+    } else {
+        run_batched(g, r, src_dev, k, bc_dev, cnt, ms, &kms);
+        launches = k > 0 ? 1 : 0;
+    }
+    check_device_errors(cnt);
+    fill_stats(g, r, cnt, k, (double)ms, (double)kms, launches, stats);
+    g->last_stats_valid = true;
+    fill_stats(g, r, cnt, k, (double)ms, (double)kms, launches, &g->last_stats);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+bc_status bc_create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                          const int32_t *w, uint32_t flags, bc_graph **out)
+{
+    return guarded([&] { create_graph(n, nnz, row_ptr, col, w, flags, out); });
+}
+
+bc_status bc_destroy_graph(bc_graph *g)
+{
+    return guarded([&] { delete g; });
+}
+
+bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info)
+{
+    return guarded([&] {
+        if (!g || !info)
+            throw bc_error(BC_E_INVAL, "null argument");
+        bc_graph_info i;
+        memset(&i, 0, sizeof i);
+        i.n = g->n;
+        i.nnz = g->nnz;
+        i.directed = g->directed;
+        i.w_max = g->wmax;
+        i.max_out_degree = g->maxdeg;
+        i.packed_arcs = g->packed;
+        i.device_bytes = (int64_t)(g->row.bytes + g->arc.bytes + g->wt.bytes + g->trow.bytes +
+                                   g->tarc.bytes + g->twt.bytes);
+        *info = i;
+    });
+}
+
+bc_status bc_compute(bc_graph *g, const int32_t *sources, int64_t k, const bc_options *opt,
+                     bc_result **out)
+{
+    return guarded([&] {
+        if (!g || !out)
+            throw bc_error(BC_E_INVAL, "null argument");
+        if (k < 0)
+            throw bc_error(BC_E_INVAL, "k must be >= 0");
+        std::vector<int32_t> all;
+        if (!sources) {
+            if (k != g->n && k != 0)
+                throw bc_error(BC_E_INVAL, "sources may be NULL only with k = n");
+            all.resize((size_t)k);
+            for (int64_t i = 0; i < k; ++i)
+                all[(size_t)i] = (int32_t)i;
+            sources = all.data();
+        }
+        for (int64_t i = 0; i < k; ++i)
+            if (sources[i] < 0 || sources[i] >= g->n)
+                throw bc_error(BC_E_INVAL, "sources[%lld] = %d out of range", (long long)i,
+                               sources[i]);
+        ResolvedOptions r = resolve_options(g, opt, k);
+        std::unique_ptr<bc_result> res(new bc_result());
+        res->n = g->n;
+        res->bc.alloc((size_t)g->n * sizeof(double));
+        ensure_sources(g, k);
+        if (k > 0)
+            hip_check(hipMemcpyAsync(g->src_buf.p, sources, (size_t)k * 4, hipMemcpyHostToDevice,
+                                     r.stream),
+                      "upload sources");
+        compute_device(g, (const int32_t *)g->src_buf.p, sources, k, opt, (double *)res->bc.p,
+                       &res->stats);
+        *out = res.release();
+    });
+}
+
+bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
+                            const bc_options *opt, double *bc_dev, bc_stats *stats)
+{
+    return guarded([&] {
+        if (!g || !bc_dev || (k > 0 && !sources_dev))
+            throw bc_error(BC_E_INVAL, "null argument");
+        if (k < 0)
+            throw bc_error(BC_E_INVAL, "k must be >= 0");
+        compute_device(g, sources_dev, nullptr, k, opt, bc_dev, stats);
+    });
+}
+
+bc_status bc_result_bc(const bc_result *r, double *bc_host)
+{
+    return guarded([&] {
+        if (!r || !bc_host)
+            throw bc_error(BC_E_INVAL, "null argument");
+        hip_check(hipMemcpy(bc_host, r->bc.p, (size_t)r->n * sizeof(double),
+                            hipMemcpyDeviceToHost),
+                  "copy result");
+    });
+}
+
+bc_status bc_result_device_ptr(const bc_result *r, const double **bc_dev)
+{
+    return guarded([&] {
+        if (!r || !bc_dev)
+            throw bc_error(BC_E_INVAL, "null argument");
+        *bc_dev = (const double *)r->bc.p;
+    });
+}
+
+bc_status bc_result_stats(const bc_result *r, bc_stats *st)
+{
+    return guarded([&] {
+        if (!r || !st)
+            throw bc_error(BC_E_INVAL, "null argument");
+        *st = r->stats;
+    });
+}
+
+bc_status bc_destroy_result(bc_result *r)
+{
+    return guarded([&] { delete r; });
+}
+
+bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t *d,
+                          uint64_t *sigma, double *delta)
+{
+    return guarded([&] {
+        if (!g)
+            throw bc_error(BC_E_INVAL, "null graph");
+        if (s < 0 || s >= g->n)
+            throw bc_error(BC_E_INVAL, "source %d out of range", s);
+        bc_options o;
+        memset(&o, 0, sizeof o);
+        if (opt)
+            o = *opt;
+        o.batch = 1;
+        o.autotune = 0;
+        ResolvedOptions r = resolve_options(g, &o, 1);
+        ensure_sources(g, 1);
+        hip_check(hipMemcpyAsync(g->src_buf.p, &s, 4, hipMemcpyHostToDevice, r.stream), "src");
+        DevBuf bc, dd, ds, dl;
+        bc.alloc((size_t)g->n * 8);
+        compute_device(g, (const int32_t *)g->src_buf.p, &s, 1, &o, (double *)bc.p, nullptr);
+        Workspace &ws = r.mode == BC_MODE_PLAIN ? g->plain : g->batched;
+        dd.alloc((size_t)g->n * 4);
+        ds.alloc((size_t)g->n * 8);
+        dl.alloc((size_t)g->n * 8);
+        hip_check(launch_export_state((char *)ws.base.p, ws.L, 0, g->n, (int32_t *)dd.p,
+                                      (uint64_t *)ds.p, (double *)dl.p, r.stream),
+                  "export");
+        hip_check(hipStreamSynchronize(r.stream), "synchronize");
+        if (d)
+            hip_check(hipMemcpy(d, dd.p, (size_t)g->n * 4, hipMemcpyDeviceToHost), "copy d");
+        if (sigma)
+            hip_check(hipMemcpy(sigma, ds.p, (size_t)g->n * 8, hipMemcpyDeviceToHost), "copy");
+        if (delta)
+            hip_check(hipMemcpy(delta, dl.p, (size_t)g->n * 8, hipMemcpyDeviceToHost), "copy");
+    });
+}
+
+double bc_algo_bytes(int32_t n, int32_t weight_bytes, int64_t arcs, int64_t reached,
+                     int64_t dag_arcs)
+{
+    return (double)arcs * (16.0 + 2.0 * weight_bytes) + 72.0 * (double)reached +
+           24.0 * (double)dag_arcs + 20.0 * (double)n;
+}
+
+const char *bc_last_error(void) { return g_last_error.c_str(); }
+
+const char *bc_version(void) { return "bcgpu 0.1 (gfx950)"; }
+
+} // extern "C"

@@ -1,0 +1,111 @@
+// bc_internal.h -- host-side objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/bc.h"
+#include "kernels.h"
+
+struct bc_error {
+    bc_status status;
+    std::string msg;
+    bc_error(bc_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+};
+
+void hip_check(hipError_t e, const char *what);
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n);
+    void release();
+};
+
+// Device counters of one computation (one block per graph).
+struct DevCounters {
+    unsigned long long next_src;
+    unsigned long long err[2];
+    unsigned long long pad;
+    DevStats stats;
+};
+
+struct Workspace {
+    DevBuf base;
+    SlabLayout L{};
+    int nslabs = 0;
+};
+
+struct ResolvedOptions {
+    int mode = BC_MODE_BATCHED;
+    int batch = 1;
+    int delta = 1;
+    int lane_max = 32;
+    int wg_threads = 256;
+    int accumulate = 1;
+    int autotune = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct TunedOptions {
+    bool valid = false;
+    int delta = 0, lane_max = 0, wg_threads = 0;
+    double best_ms_per_source = 0.0;
+};
+
+struct bc_graph {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    bool directed = false;
+    int32_t wmax = 1;
+    int32_t maxdeg = 0;
+    int wbytes = 1;
+    double avg_deg = 0.0, wmean = 1.0;
+    bool packed = false;
+    uint32_t wshift = 0, wmask = 0;
+    int device = 0;
+    int num_cus = 1;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr; // around the main kernel launch
+
+    DevBuf row, arc, wt;    // out-arcs
+    DevBuf trow, tarc, twt; // in-arcs (directed graphs only)
+    DevBuf dnode, deg;      // per-vertex minimum out-weight and out-degree
+    DevBuf ctl;             // DevCounters
+    DevBuf plain_ctl;       // PlainCtl
+    DevBuf src_buf;         // uploaded source lists
+    DevCounters *host_counters = nullptr;
+    PlainCtl *host_plain = nullptr;
+    bool plain_ctl_ready = false;
+    long long plain_gen_hint = 0;
+
+    Workspace batched, plain;
+    TunedOptions tuned;
+    bool last_stats_valid = false;
+    bc_stats last_stats{};
+
+    DevGraph view() const;
+    ~bc_graph();
+};
+
+struct bc_result {
+    int32_t n = 0;
+    DevBuf bc;
+    bc_stats stats{};
+};
+
+SlabLayout slab_layout(int32_t n);
+int default_delta(const bc_graph *g);
+int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc);
+ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
+void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
+                    const bc_options *opt, double *bc_dev, bc_stats *stats);
+void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int32_t *src_dev,
+              int64_t k);
+void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
+                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms);

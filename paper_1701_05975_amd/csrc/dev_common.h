@@ -1,0 +1,107 @@
+// dev_common.h -- device-side building blocks shared by the batched and the
+// plain forms of the betweenness kernels (gfx950, 64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shared_types.h"
+
+template <bool PACKED>
+__device__ __forceinline__ void arc_at(const uint32_t *arc, const int32_t *wt, uint32_t e,
+                                       uint32_t wshift, uint32_t wmask, uint32_t &head,
+                                       uint32_t &w)
+{
+    uint32_t a = arc[e];
+    if constexpr (PACKED) {
+        head = a >> wshift;
+        w = (a & wmask) + 1u;
+    } else {
+        head = a;
+        w = (uint32_t)wt[e];
+    }
+}
+
+__device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slot)
+{
+    char *p = base + (size_t)slot * L.stride;
+    Slab s;
+    s.d = (uint32_t *)(p + L.d);
+    s.sigma = (uint64_t *)(p + L.sigma);
+    s.delta = (double *)(p + L.delta);
+    s.bcp = (double *)(p + L.bcp);
+    s.stamp = (int32_t *)(p + L.stamp);
+    s.infar = (int32_t *)(p + L.infar);
+    s.order = (int32_t *)(p + L.order);
+    s.qa = (int32_t *)(p + L.qa);
+    s.qb = (int32_t *)(p + L.qb);
+    s.fa = (int32_t *)(p + L.fa);
+    s.fb = (int32_t *)(p + L.fb);
+    s.band_off = (int32_t *)(p + L.band_off);
+    s.hdr = (int64_t *)(p + L.hdr);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Wave-aggregated slot allocation on a counter (LDS or global): every active
+// lane with `pred` gets a distinct index; one atomic per wave.
+__device__ __forceinline__ int wave_alloc(int *counter, bool pred)
+{
+    uint64_t mask = __ballot(pred);
+    if (mask == 0)
+        return -1;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == leader)
+        base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader);
+    return pred ? base + (int)lanes_below(mask) : -1;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = __shfl_xor(x, o);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        x += __shfl_xor(x, o);
+    return x;
+}
+
+// Sum of unsigned 64-bit values across the wave with wrap detection.
+__device__ __forceinline__ uint64_t wave_sum_u64_checked(uint64_t x, bool &ovf)
+{
+    bool o = ovf;
+    for (int k = 32; k > 0; k >>= 1) {
+        uint64_t y = __shfl_xor(x, k);
+        uint64_t t = x + y;
+        o |= t < x;
+        x = t;
+    }
+    ovf = __ballot(o) != 0;
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int k = 32; k > 0; k >>= 1)
+        x += __shfl_xor(x, k);
+    return x;
+}
+

@@ -1,0 +1,69 @@
+// kernels.h -- argument blocks and launchers shared by the host runtime and
+// the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shared_types.h"
+
+struct BatchArgs {
+    DevGraph g;
+    char *slab_base;
+    SlabLayout L;
+    const int32_t *sources;
+    long long k;
+    unsigned long long *next_src; // device counter handing out sources
+    double *bc_out;               // output (atomic accumulation mode)
+    uint32_t delta;               // band width
+    int lane_max;
+    DevStats *stats;
+    unsigned long long *err;      // [0] error bits, [1] first overflowing source index
+};
+
+// Phase machine of the plain form (device memory, one per graph).
+struct PlainCtl {
+    int phase;
+    int32_t s;
+    long long src_idx;
+    int near_len, next_cnt, order_cnt, far_cnt, kept_cnt, pend_len, pend_cnt;
+    int cur, fcur, pcur;
+    int32_t gen, band_gen;
+    uint32_t thr, thr_old, far_min;
+    int band_start, nbands, dband, round, b0, b1;
+    unsigned long long iters, iter_cap;
+    int abort, finished;
+    unsigned long long srounds, drounds;
+};
+
+struct PlainArgs {
+    DevGraph g;
+    char *slab_base;
+    SlabLayout L;
+    PlainCtl *ctl;
+    double *bc_out;
+    uint32_t delta;
+    int lane_max;
+    DevStats *stats;
+    unsigned long long *err;
+};
+
+hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
+                          hipStream_t st);
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc);
+hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
+                                  double *out, hipStream_t st);
+hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,
+                               long long idx, bool clear_stamps, hipStream_t st);
+hipError_t launch_plain_steps(const PlainArgs &a, bool packed, int grid, int pairs,
+                              hipStream_t st);
+hipError_t launch_plain_clear_infar(const PlainArgs &a, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
+                           hipStream_t st);
+hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, int n,
+                             hipStream_t st);
+hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, int n, int32_t *d,
+                               uint64_t *sigma, double *delta, hipStream_t st);
+hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
+                                    hipStream_t st);

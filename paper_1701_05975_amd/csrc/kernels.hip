@@ -1,0 +1,859 @@
+// kernels.hip -- HIP kernels of the betweenness library (gfx950).
+//
+// Batched form: a persistent launch of B workgroups, one state slab each;
+// every workgroup takes sources from a device counter and runs the whole
+// per-source pipeline with workgroup barriers only (one block per root
+// vertex with the block's threads sharing that source, Sec. 3.1).
+//
+// Plain form: one source at a time on the whole GPU; a one-thread control
+// kernel advances a phase machine held in device memory and a grid-wide step
+// kernel executes the current phase, so the host only launches pairs of
+// kernels and polls for completion now and then.
+#include "kernels.h"
+#include "dev_common.h"
+#include "passes.h"
+
+#define WG_SCOPE __HIP_MEMORY_SCOPE_WORKGROUP
+#define AG_SCOPE __HIP_MEMORY_SCOPE_AGENT
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+struct WgCtl {
+    int near_len, next_cnt, order_cnt, far_cnt, kept_cnt, pend_cnt;
+    int cur, fcur;
+    int32_t gen, band_gen;
+    uint32_t thr, thr_old, far_min;
+    int band_start, nbands;
+    int abort;
+    long long src_idx;
+    unsigned long long iters;
+    unsigned int bands, srounds, drounds;
+};
+
+// Runs the count (or dependency) rounds over the members order[b0, b1) of
+// one band inside a workgroup.  Returns false if the round bound tripped.
+template <bool PACKED, int NT, bool SIGMA, bool ATOMIC_BC>
+__device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const BatchArgs &a,
+                               int32_t s, long long idx, int b0, int b1, double *bc,
+                               uint64_t &st_arcs, uint64_t &st_dag)
+{
+    const int tid = threadIdx.x;
+    const int32_t *items = S.order + b0;
+    int len = b1 - b0;
+    int which = 0;
+    const int cap = len + 2;
+    for (int round = 0;; ++round) {
+        if (tid == 0)
+            C.pend_cnt = 0;
+        __syncthreads();
+        RoundCtx rc;
+        rc.items = items;
+        rc.len = len;
+        rc.worker = tid / WAVE;
+        rc.nworkers = NT / WAVE;
+        rc.lane_max = a.lane_max;
+        rc.s = s;
+        rc.src_idx = idx;
+        rc.first_round = round == 0;
+        rc.pend_q = which ? S.qb : S.qa;
+        rc.pend_cnt = &C.pend_cnt;
+        rc.err = a.err;
+        if (SIGMA)
+            sigma_round<PACKED, WG_SCOPE>(g, S, rc, st_arcs, st_dag);
+        else
+            delta_round<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, rc, bc);
+        __syncthreads();
+        const int nl = C.pend_cnt;
+        __syncthreads(); // everyone has read pend_cnt before it is touched again
+        if (tid == 0) {
+            if (SIGMA)
+                C.srounds++;
+            else
+                C.drounds++;
+        }
+        if (nl == 0)
+            return true;
+        if (round + 1 >= cap)
+            return false;
+        items = which ? S.qb : S.qa;
+        which ^= 1;
+        len = nl;
+    }
+}
+
+template <bool PACKED, int NT, bool ATOMIC_BC>
+__global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
+{
+    __shared__ WgCtl C;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const DevGraph &g = a.g;
+    const int n = g.n;
+    Slab S = slab_at(a.slab_base, a.L, blockIdx.x);
+    double *bc = ATOMIC_BC ? a.bc_out : S.bcp;
+    if (!ATOMIC_BC)
+        for (int v = tid; v < n; v += NT)
+            S.bcp[v] = 0.0;
+    uint64_t st_arcs = 0, st_dag = 0, st_imp = 0;
+    if (tid == 0) {
+        C.gen = (int32_t)S.hdr[0];
+        C.iters = 0;
+        C.bands = C.srounds = C.drounds = 0;
+    }
+    __syncthreads();
+    const unsigned long long iter_cap = 8ull * (unsigned long long)n + 1024ull;
+
+    for (;;) {
+        if (tid == 0)
+            C.src_idx = (long long)atomicAdd(a.next_src, 1ull);
+        __syncthreads();
+        const long long idx = C.src_idx;
+        if (idx >= a.k)
+            break;
+        const int32_t s = a.sources[idx];
+
+        // Queue tags only grow; restart them long before they could wrap.
+        if (C.gen > (1 << 30)) {
+            for (int v = tid; v < n; v += NT)
+                S.stamp[v] = 0;
+            __syncthreads();
+            if (tid == 0)
+                C.gen = 0;
+        }
+        // Initialisation (Alg. 1): d = inf and sigma = 0 everywhere.
+        for (int v = tid; v < n; v += NT) {
+            S.d[v] = BC_INF;
+            S.sigma[v] = 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            S.d[s] = 0;
+            S.sigma[s] = 1;
+            C.gen += 1;
+            S.stamp[s] = C.gen;
+            S.qa[0] = s;
+            S.order[0] = s;
+            S.band_off[0] = 0;
+            C.cur = 0;
+            C.fcur = 0;
+            C.near_len = 1;
+            C.next_cnt = 0;
+            C.order_cnt = 1;
+            C.far_cnt = 0;
+            C.band_gen = C.gen;
+            C.thr = a.delta;
+            C.far_min = BC_INF;
+            C.band_start = 0;
+            C.nbands = 0;
+            C.abort = 0;
+            C.iters = 0;
+        }
+        __syncthreads();
+
+        // Forward pass: near-far bands of width delta.
+        for (;;) {
+            while (C.near_len > 0) {
+                ExpandCtx ec;
+                ec.items = C.cur ? S.qb : S.qa;
+                ec.len = C.near_len;
+                ec.worker = tid / WAVE;
+                ec.nworkers = NT / WAVE;
+                ec.thr = C.thr;
+                ec.tag_next = C.gen + 1;
+                ec.band_gen = C.band_gen;
+                ec.lane_max = a.lane_max;
+                ec.next_q = C.cur ? S.qa : S.qb;
+                ec.next_cnt = &C.next_cnt;
+                ec.order = S.order;
+                ec.order_cnt = &C.order_cnt;
+                ec.far_q = C.fcur ? S.fb : S.fa;
+                ec.far_cnt = &C.far_cnt;
+                uint32_t fmin = BC_INF;
+                expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, st_imp);
+                fmin = wave_min_u32(fmin);
+                if (lane == 0 && fmin != BC_INF)
+                    atomicMin(&C.far_min, fmin);
+                __syncthreads();
+                if (tid == 0) {
+                    C.cur ^= 1;
+                    C.near_len = C.next_cnt;
+                    C.next_cnt = 0;
+                    C.gen += 1;
+                    if (++C.iters > iter_cap) {
+                        C.abort = 1;
+                        C.near_len = 0;
+                    }
+                }
+                __syncthreads();
+            }
+            if (C.abort)
+                break;
+            // The band is closed: its members order[b0, b1) have final distances.
+            const int b0 = C.band_start, b1 = C.order_cnt;
+            if (b1 > b0) {
+                if (!wg_band_rounds<PACKED, NT, true, ATOMIC_BC>(g, S, C, a, s, idx, b0, b1, bc,
+                                                                  st_arcs, st_dag)) {
+                    if (tid == 0)
+                        C.abort = 1;
+                    __syncthreads();
+                    break;
+                }
+            }
+            if (tid == 0) {
+                if (b1 > b0) {
+                    C.nbands += 1;
+                    S.band_off[C.nbands] = b1;
+                }
+                C.band_start = b1;
+            }
+            __syncthreads();
+            if (C.far_cnt == 0)
+                break;
+            // Next band: threshold from the least far distance seen.
+            if (tid == 0) {
+                C.thr_old = C.thr;
+                const uint32_t lo = C.far_min > C.thr ? C.far_min : C.thr;
+                const uint64_t t = (uint64_t)lo + a.delta;
+                C.thr = t > BC_INF ? BC_INF : (uint32_t)t;
+                C.far_min = BC_INF;
+                C.gen += 1;
+                C.band_gen = C.gen;
+                C.near_len = 0;
+                C.kept_cnt = 0;
+                if (++C.iters > iter_cap)
+                    C.abort = 1;
+            }
+            __syncthreads();
+            if (C.abort)
+                break;
+            {
+                SplitCtx sp;
+                sp.far_in = C.fcur ? S.fb : S.fa;
+                sp.len = C.far_cnt;
+                sp.worker = tid / WAVE;
+                sp.nworkers = NT / WAVE;
+                sp.thr_old = C.thr_old;
+                sp.thr = C.thr;
+                sp.tag = C.gen;
+                sp.near_q = C.cur ? S.qb : S.qa;
+                sp.near_cnt = &C.near_len;
+                sp.order = S.order;
+                sp.order_cnt = &C.order_cnt;
+                sp.far_out = C.fcur ? S.fa : S.fb;
+                sp.kept_cnt = &C.kept_cnt;
+                uint32_t kmin = BC_INF;
+                split_pass(S, sp, kmin);
+                kmin = wave_min_u32(kmin);
+                if (lane == 0 && kmin != BC_INF)
+                    atomicMin(&C.far_min, kmin);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                C.fcur ^= 1;
+                C.far_cnt = C.kept_cnt;
+            }
+            __syncthreads();
+        }
+
+        // Backward pass: bands in reverse order (Alg. 3).
+        if (!C.abort) {
+            const int nb = C.nbands;
+            for (int b = nb - 1; b >= 0; --b) {
+                const int b0 = S.band_off[b], b1 = S.band_off[b + 1];
+                if (!wg_band_rounds<PACKED, NT, false, ATOMIC_BC>(g, S, C, a, s, idx, b0, b1, bc,
+                                                                   st_arcs, st_dag)) {
+                    if (tid == 0)
+                        C.abort = 1;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (C.abort) {
+            // Leave the slab reusable and report; the result is not valid.
+            for (int v = tid; v < n; v += NT)
+                S.infar[v] = 0;
+            if (tid == 0)
+                atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_INTERNAL);
+        }
+        if (tid == 0) {
+            atomicAdd(&a.stats->reached, (unsigned long long)C.order_cnt);
+            atomicAdd(&a.stats->bands, (unsigned long long)C.nbands);
+            atomicAdd(&a.stats->iterations, C.iters);
+        }
+        __syncthreads();
+    }
+
+    // Flush per-lane statistics: one atomic per wave.
+    {
+        unsigned long long x;
+        x = st_arcs;
+        for (int o = 32; o > 0; o >>= 1)
+            x += __shfl_xor(x, o);
+        if (lane == 0)
+            atomicAdd(&a.stats->arcs, x);
+        x = st_dag;
+        for (int o = 32; o > 0; o >>= 1)
+            x += __shfl_xor(x, o);
+        if (lane == 0)
+            atomicAdd(&a.stats->dag, x);
+        x = st_imp;
+        for (int o = 32; o > 0; o >>= 1)
+            x += __shfl_xor(x, o);
+        if (lane == 0)
+            atomicAdd(&a.stats->improvements, x);
+    }
+    if (tid == 0) {
+        S.hdr[0] = C.gen;
+        atomicAdd(&a.stats->sigma_rounds, (unsigned long long)C.srounds);
+        atomicAdd(&a.stats->delta_rounds, (unsigned long long)C.drounds);
+    }
+}
+
+// Sum of the per-slab partial centralities, slab after slab.
+__global__ void k_reduce_partials(char *slab_base, SlabLayout L, int nslabs, int n, double *out)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int b = 0; b < nslabs; ++b)
+            acc += ((const double *)(slab_base + (size_t)b * L.stride + L.bcp))[v];
+        out[v] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain form
+// ---------------------------------------------------------------------------
+enum { PH_EXPAND = 0, PH_SIGMA = 1, PH_SPLIT = 2, PH_DELTA = 3, PH_DONE = 4 };
+
+__device__ void plain_start_delta(PlainCtl *c, const Slab &S)
+{
+    c->dband = c->nbands - 1;
+    if (c->dband < 0) {
+        c->phase = PH_DONE;
+        return;
+    }
+    c->b0 = S.band_off[c->dband];
+    c->b1 = S.band_off[c->dband + 1];
+    c->round = 0;
+    c->pend_cnt = 0;
+    c->phase = PH_DELTA;
+}
+
+// A band is finished (its counts are final): record it, then either start
+// the backward pass or open the next band by splitting the far pile.
+__device__ void plain_end_band(PlainCtl *c, const Slab &S, uint32_t delta)
+{
+    if (c->b1 > c->b0) {
+        c->nbands += 1;
+        S.band_off[c->nbands] = c->b1;
+    }
+    c->band_start = c->b1;
+    if (c->far_cnt == 0) {
+        plain_start_delta(c, S);
+        return;
+    }
+    c->thr_old = c->thr;
+    const uint32_t lo = c->far_min > c->thr ? c->far_min : c->thr;
+    const uint64_t t = (uint64_t)lo + delta;
+    c->thr = t > BC_INF ? BC_INF : (uint32_t)t;
+    c->far_min = BC_INF;
+    c->gen += 1;
+    c->band_gen = c->gen;
+    c->near_len = 0;
+    c->kept_cnt = 0;
+    c->iters += 1;
+    c->phase = PH_SPLIT;
+}
+
+__global__ void k_plain_init(PlainArgs a)
+{
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.g.n; v += gridDim.x * blockDim.x) {
+        S.d[v] = BC_INF;
+        S.sigma[v] = 0;
+    }
+}
+
+__global__ void k_plain_setup(PlainArgs a, int32_t s, long long idx)
+{
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    PlainCtl *c = a.ctl;
+    S.d[s] = 0;
+    S.sigma[s] = 1;
+    c->gen += 1;
+    S.stamp[s] = c->gen;
+    S.qa[0] = s;
+    S.order[0] = s;
+    S.band_off[0] = 0;
+    c->s = s;
+    c->src_idx = idx;
+    c->cur = 0;
+    c->fcur = 0;
+    c->pcur = 0;
+    c->near_len = 1;
+    c->next_cnt = 0;
+    c->order_cnt = 1;
+    c->far_cnt = 0;
+    c->kept_cnt = 0;
+    c->pend_cnt = 0;
+    c->pend_len = 0;
+    c->band_gen = c->gen;
+    c->thr = a.delta;
+    c->thr_old = 0;
+    c->far_min = BC_INF;
+    c->band_start = 0;
+    c->nbands = 0;
+    c->round = 0;
+    c->b0 = c->b1 = 0;
+    c->iters = 0;
+    c->abort = 0;
+    c->finished = 0;
+    c->srounds = 0;
+    c->drounds = 0;
+    c->phase = PH_EXPAND;
+}
+
+// Restarts the queue tags (they only grow) long before they could wrap.
+__global__ void k_plain_clear_stamps(PlainArgs a)
+{
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.g.n; v += gridDim.x * blockDim.x)
+        S.stamp[v] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        a.ctl->gen = 0;
+}
+
+template <bool PACKED>
+__global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
+{
+    PlainCtl *c = a.ctl;
+    const int phase = c->phase;
+    if (phase == PH_DONE)
+        return;
+    const DevGraph &g = a.g;
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    const int worker = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    const int nworkers = (int)(gridDim.x * blockDim.x / WAVE);
+    const int lane = lane_id();
+    if (phase == PH_EXPAND) {
+        ExpandCtx ec;
+        ec.items = c->cur ? S.qb : S.qa;
+        ec.len = c->near_len;
+        ec.worker = worker;
+        ec.nworkers = nworkers;
+        ec.thr = c->thr;
+        ec.tag_next = c->gen + 1;
+        ec.band_gen = c->band_gen;
+        ec.lane_max = a.lane_max;
+        ec.next_q = c->cur ? S.qa : S.qb;
+        ec.next_cnt = &c->next_cnt;
+        ec.order = S.order;
+        ec.order_cnt = &c->order_cnt;
+        ec.far_q = c->fcur ? S.fb : S.fa;
+        ec.far_cnt = &c->far_cnt;
+        uint32_t fmin = BC_INF;
+        uint64_t imp = 0;
+        expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, imp);
+        fmin = wave_min_u32(fmin);
+        unsigned long long x = imp;
+        for (int o = 32; o > 0; o >>= 1)
+            x += __shfl_xor(x, o);
+        if (lane == 0) {
+            if (fmin != BC_INF)
+                atomicMin(&c->far_min, fmin);
+            if (x)
+                atomicAdd(&a.stats->improvements, x);
+        }
+    } else if (phase == PH_SPLIT) {
+        SplitCtx sp;
+        sp.far_in = c->fcur ? S.fb : S.fa;
+        sp.len = c->far_cnt;
+        sp.worker = worker;
+        sp.nworkers = nworkers;
+        sp.thr_old = c->thr_old;
+        sp.thr = c->thr;
+        sp.tag = c->gen;
+        sp.near_q = c->cur ? S.qb : S.qa;
+        sp.near_cnt = &c->near_len;
+        sp.order = S.order;
+        sp.order_cnt = &c->order_cnt;
+        sp.far_out = c->fcur ? S.fa : S.fb;
+        sp.kept_cnt = &c->kept_cnt;
+        uint32_t kmin = BC_INF;
+        split_pass(S, sp, kmin);
+        kmin = wave_min_u32(kmin);
+        if (lane == 0 && kmin != BC_INF)
+            atomicMin(&c->far_min, kmin);
+    } else {
+        RoundCtx rc;
+        const bool first = c->round == 0;
+        rc.items = first ? S.order + c->b0 : (c->pcur ? S.qb : S.qa);
+        rc.len = first ? c->b1 - c->b0 : c->pend_len;
+        rc.worker = worker;
+        rc.nworkers = nworkers;
+        rc.lane_max = a.lane_max;
+        rc.s = c->s;
+        rc.src_idx = c->src_idx;
+        rc.first_round = first;
+        rc.pend_q = first ? S.qa : (c->pcur ? S.qa : S.qb);
+        rc.pend_cnt = &c->pend_cnt;
+        rc.err = a.err;
+        if (phase == PH_SIGMA) {
+            uint64_t arcs = 0, dag = 0;
+            sigma_round<PACKED, AG_SCOPE>(g, S, rc, arcs, dag);
+            unsigned long long x = arcs, y = dag;
+            for (int o = 32; o > 0; o >>= 1) {
+                x += __shfl_xor(x, o);
+                y += __shfl_xor(y, o);
+            }
+            if (lane == 0) {
+                if (x)
+                    atomicAdd(&a.stats->arcs, x);
+                if (y)
+                    atomicAdd(&a.stats->dag, y);
+            }
+        } else {
+            delta_round<PACKED, AG_SCOPE, false>(g, S, rc, a.bc_out);
+        }
+    }
+}
+
+__global__ void k_plain_control(PlainArgs a)
+{
+    PlainCtl *c = a.ctl;
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    switch (c->phase) {
+    case PH_EXPAND:
+        c->cur ^= 1;
+        c->near_len = c->next_cnt;
+        c->next_cnt = 0;
+        c->gen += 1;
+        c->iters += 1;
+        if (c->near_len == 0) {
+            c->b0 = c->band_start;
+            c->b1 = c->order_cnt;
+            c->round = 0;
+            c->pend_cnt = 0;
+            if (c->b1 > c->b0)
+                c->phase = PH_SIGMA;
+            else
+                plain_end_band(c, S, a.delta);
+        }
+        break;
+    case PH_SIGMA:
+        c->srounds += 1;
+        if (c->pend_cnt > 0) {
+            c->pcur = c->round == 0 ? 0 : c->pcur ^ 1;
+            c->pend_len = c->pend_cnt;
+            c->pend_cnt = 0;
+            c->round += 1;
+            if (c->round > c->b1 - c->b0 + 2)
+                c->abort = 1;
+        } else {
+            plain_end_band(c, S, a.delta);
+        }
+        break;
+    case PH_SPLIT:
+        c->fcur ^= 1;
+        c->far_cnt = c->kept_cnt;
+        c->kept_cnt = 0;
+        if (c->near_len > 0) {
+            c->phase = PH_EXPAND;
+        } else {
+            c->b0 = c->b1 = c->band_start;
+            plain_end_band(c, S, a.delta);
+        }
+        break;
+    case PH_DELTA:
+        c->drounds += 1;
+        if (c->pend_cnt > 0) {
+            c->pcur = c->round == 0 ? 0 : c->pcur ^ 1;
+            c->pend_len = c->pend_cnt;
+            c->pend_cnt = 0;
+            c->round += 1;
+            if (c->round > c->b1 - c->b0 + 2)
+                c->abort = 1;
+        } else {
+            c->dband -= 1;
+            if (c->dband < 0) {
+                c->phase = PH_DONE;
+            } else {
+                c->b0 = S.band_off[c->dband];
+                c->b1 = S.band_off[c->dband + 1];
+                c->round = 0;
+                c->pend_cnt = 0;
+            }
+        }
+        break;
+    default:
+        break;
+    }
+    if (c->phase != PH_DONE && (c->abort || c->iters > c->iter_cap)) {
+        c->abort = 1;
+        c->phase = PH_DONE;
+    }
+    if (c->phase == PH_DONE && !c->finished) {
+        c->finished = 1;
+        if (c->abort) {
+            atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_INTERNAL);
+        }
+        a.stats->reached += (unsigned long long)c->order_cnt;
+        a.stats->bands += (unsigned long long)c->nbands;
+        a.stats->iterations += c->iters;
+        a.stats->sigma_rounds += c->srounds;
+        a.stats->delta_rounds += c->drounds;
+    }
+}
+
+__global__ void k_plain_clear_infar(PlainArgs a)
+{
+    Slab S = slab_at(a.slab_base, a.L, 0);
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.g.n; v += gridDim.x * blockDim.x)
+        S.infar[v] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t value)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, size_t count, unsigned long long value)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// Clears the persistent parts of every slab (queue tags, far flags, header).
+__global__ void k_slab_reset(char *slab_base, SlabLayout L, int nslabs, int n)
+{
+    const int slot = blockIdx.y;
+    if (slot >= nslabs)
+        return;
+    Slab S = slab_at(slab_base, L, slot);
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        S.stamp[v] = 0;
+        S.infar[v] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        S.hdr[0] = 0;
+}
+
+// Copies one slab's per-source state out, with unreached vertices shown as
+// (INT32_MAX, 0, 0).
+__global__ void k_export_state(char *slab_base, SlabLayout L, int slot, int n, int32_t *d,
+                               uint64_t *sigma, double *delta)
+{
+    Slab S = slab_at(slab_base, L, slot);
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t dv = S.d[v];
+        const bool r = dv != BC_INF;
+        d[v] = (int32_t)dv;
+        sigma[v] = r ? S.sigma[v] : 0ull;
+        delta[v] = r ? S.delta[v] : 0.0;
+    }
+}
+
+// Minimum outgoing weight per vertex (Delta_node of Sec. 3.2; INT32_MAX when
+// the vertex has no arcs) and the out-degree.
+template <bool PACKED>
+__global__ void k_graph_vertex_info(DevGraph g, int32_t *dnode, int32_t *deg)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const uint32_t b = g.row[v], e = g.row[v + 1];
+        uint32_t m = BC_INF;
+        for (uint32_t j = b; j < e; ++j) {
+            uint32_t u, w;
+            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
+            m = w < m ? w : m;
+        }
+        dnode[v] = (int32_t)m;
+        deg[v] = (int32_t)(e - b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <bool PACKED, int NT, bool ATOMIC>
+static void launch_batched_t(const BatchArgs &a, int nslabs, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC>), dim3(nslabs), dim3(NT), 0, st, a);
+}
+
+hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
+                          hipStream_t st)
+{
+#define BC_CASE(P, T, A)                                                                        \
+    if (packed == P && nt == T && atomic_bc == A) {                                             \
+        launch_batched_t<P, T, A>(a, nslabs, st);                                               \
+        return hipGetLastError();                                                               \
+    }
+    BC_CASE(true, 256, false)
+    BC_CASE(true, 256, true)
+    BC_CASE(true, 512, false)
+    BC_CASE(true, 512, true)
+    BC_CASE(true, 1024, false)
+    BC_CASE(true, 1024, true)
+    BC_CASE(false, 256, false)
+    BC_CASE(false, 256, true)
+    BC_CASE(false, 512, false)
+    BC_CASE(false, 512, true)
+    BC_CASE(false, 1024, false)
+    BC_CASE(false, 1024, true)
+#undef BC_CASE
+    return hipErrorInvalidValue;
+}
+
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc)
+{
+    int blocks = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define BC_OCC(P, T, A)                                                                         \
+    if (packed == P && nt == T && atomic_bc == A)                                               \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A>, T, 0);
+    BC_OCC(true, 256, false)
+    BC_OCC(true, 256, true)
+    BC_OCC(true, 512, false)
+    BC_OCC(true, 512, true)
+    BC_OCC(true, 1024, false)
+    BC_OCC(true, 1024, true)
+    BC_OCC(false, 256, false)
+    BC_OCC(false, 256, true)
+    BC_OCC(false, 512, false)
+    BC_OCC(false, 512, true)
+    BC_OCC(false, 1024, false)
+    BC_OCC(false, 1024, true)
+#undef BC_OCC
+    if (e != hipSuccess || blocks < 1) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks;
+}
+
+hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
+                                  double *out, hipStream_t st)
+{
+    int blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, st, slab_base, L, nslabs, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,
+                               long long idx, bool clear_stamps, hipStream_t st)
+{
+    int fb = (a.g.n + 255) / 256;
+    if (fb > 2048)
+        fb = 2048;
+    if (fb < 1)
+        fb = 1;
+    if (clear_stamps)
+        hipLaunchKernelGGL(k_plain_clear_stamps, dim3(fb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_plain_init, dim3(fb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_plain_setup, dim3(1), dim3(1), 0, st, a, s, idx);
+    (void)packed;
+    (void)grid;
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_steps(const PlainArgs &a, bool packed, int grid, int pairs,
+                              hipStream_t st)
+{
+    for (int i = 0; i < pairs; ++i) {
+        if (packed)
+            hipLaunchKernelGGL(k_plain_step<true>, dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_plain_step<false>, dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_plain_control, dim3(1), dim3(1), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_clear_infar(const PlainArgs &a, hipStream_t st)
+{
+    int fb = (a.g.n + 255) / 256;
+    if (fb > 2048)
+        fb = 2048;
+    if (fb < 1)
+        fb = 1;
+    hipLaunchKernelGGL(k_plain_clear_infar, dim3(fb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t st)
+{
+    if (count == 0)
+        return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
+                           hipStream_t st)
+{
+    if (count == 0)
+        return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, int n,
+                             hipStream_t st)
+{
+    int bx = (n + 255) / 256;
+    if (bx > 256)
+        bx = 256;
+    if (bx < 1)
+        bx = 1;
+    hipLaunchKernelGGL(k_slab_reset, dim3(bx, nslabs), dim3(256), 0, st, slab_base, L, nslabs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, int n, int32_t *d,
+                               uint64_t *sigma, double *delta, hipStream_t st)
+{
+    int blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_export_state, dim3(blocks), dim3(256), 0, st, slab_base, L, slot, n, d,
+                       sigma, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
+                                    hipStream_t st)
+{
+    int blocks = (g.n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    if (packed)
+        hipLaunchKernelGGL(k_graph_vertex_info<true>, dim3(blocks), dim3(256), 0, st, g, dnode,
+                           deg);
+    else
+        hipLaunchKernelGGL(k_graph_vertex_info<false>, dim3(blocks), dim3(256), 0, st, g, dnode,
+                           deg);
+    return hipGetLastError();
+}

@@ -1,0 +1,434 @@
+// passes.h -- the per-source steps of weighted Brandes, written as wave-level
+// routines over a list of vertices.  The batched form calls them with the
+// waves of one workgroup and counters in LDS; the plain form with every wave
+// of the grid and counters in global memory.
+//
+// Mapping of vertices to lanes (the warp-centric idea of Sec. 3.4 recast for
+// 64-lane wavefronts): a vertex with at most `lane_max` arcs is handled by
+// one lane, which walks its arcs in order; a vertex with more arcs is handled
+// by the whole wave, the 64 lanes striding over its arcs together.  Only
+// queued vertices get lanes (the work-efficient queue of Sec. 3.3).
+#pragma once
+
+#include "dev_common.h"
+
+template <int SCOPE>
+__device__ __forceinline__ uint32_t atomic_min_u32(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ int atomic_xchg_i32(int32_t *p, int32_t v)
+{
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ uint64_t load_u64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ void store_u64(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ double load_f64(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ void store_f64(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, SCOPE);
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass, frontier expansion (Alg. 2 relaxation step over the queue of
+// Alg. 5; near-far banding instead of the Eq. 4 settle rule).
+//
+// Every arc (v, u, w) of a queued vertex v proposes d[v] + w for u; atomicMin
+// keeps the least.  A lane that lowered d[u] below the band threshold puts u
+// in the next near queue (once per queue, by tag) and, the first time in this
+// band, in the band's member list; a lower value at or above the threshold
+// sends u to the far pile (once, by flag).
+// ---------------------------------------------------------------------------
+struct ExpandCtx {
+    const int32_t *items;
+    int len;
+    int worker, nworkers; // wave index and wave count over the item list
+    uint32_t thr;         // band threshold: d < thr is near
+    int32_t tag_next;     // tag of the queue being filled
+    int32_t band_gen;     // tag of the band's first queue
+    int lane_max;
+    int32_t *next_q;
+    int *next_cnt;
+    int32_t *order;
+    int *order_cnt;
+    int32_t *far_q;
+    int *far_cnt;
+};
+
+template <int SCOPE>
+__device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
+                                      uint32_t &far_min, uint64_t &nimp)
+{
+    bool imp = false;
+    if (nd < S.d[u]) {
+        uint32_t old = atomic_min_u32<SCOPE>(&S.d[u], nd);
+        imp = nd < old;
+    }
+    bool pn = false, pm = false, pf = false;
+    if (imp) {
+        ++nimp;
+        if (nd < c.thr) {
+            int32_t ot = atomic_xchg_i32<SCOPE>(&S.stamp[u], c.tag_next);
+            pn = ot != c.tag_next;
+            pm = ot < c.band_gen;
+        } else {
+            far_min = nd < far_min ? nd : far_min;
+            pf = atomic_xchg_i32<SCOPE>(&S.infar[u], 1) == 0;
+        }
+    }
+    if (__ballot(imp)) {
+        int k = wave_alloc(c.next_cnt, pn);
+        if (pn)
+            c.next_q[k] = (int32_t)u;
+        k = wave_alloc(c.order_cnt, pm);
+        if (pm)
+            c.order[k] = (int32_t)u;
+        k = wave_alloc(c.far_cnt, pf);
+        if (pf)
+            c.far_q[k] = (int32_t)u;
+    }
+}
+
+template <bool PACKED, int SCOPE>
+__device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c,
+                            uint32_t &far_min, uint64_t &nimp)
+{
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        uint32_t beg = 0, end = 0, dv = BC_INF;
+        if (valid) {
+            const int v = c.items[i];
+            beg = g.row[v];
+            end = g.row[v + 1];
+            dv = S.d[v];
+        }
+        const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
+        if (valid && !heavy) {
+            for (uint32_t e = beg; e < end; ++e) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+                relax<SCOPE>(S, c, u, dv + w, far_min, nimp);
+            }
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hb = (uint32_t)__shfl((int)beg, l);
+            const uint32_t he = (uint32_t)__shfl((int)end, l);
+            const uint32_t hd = (uint32_t)__shfl((int)dv, l);
+            for (uint32_t e = hb + lane; e < he; e += WAVE) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+                relax<SCOPE>(S, c, u, hd + w, far_min, nimp);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Far pile split at a band change.  Entries whose distance dropped below the
+// previous threshold were settled through the near queue already (dropped);
+// entries below the new threshold move to the near queue and become members
+// of the new band; the rest stay in the far pile.
+// ---------------------------------------------------------------------------
+struct SplitCtx {
+    const int32_t *far_in;
+    int len;
+    int worker, nworkers;
+    uint32_t thr_old, thr;
+    int32_t tag;
+    int32_t *near_q;
+    int *near_cnt;
+    int32_t *order;
+    int *order_cnt;
+    int32_t *far_out;
+    int *kept_cnt;
+};
+
+__device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uint32_t &kept_min)
+{
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        int32_t v = 0;
+        uint32_t dv = 0;
+        if (valid) {
+            v = c.far_in[i];
+            dv = S.d[v];
+        }
+        const bool drop = valid && dv < c.thr_old;
+        const bool move = valid && !drop && dv < c.thr;
+        const bool keep = valid && !drop && !move;
+        if (drop || move)
+            S.infar[v] = 0;
+        if (move)
+            S.stamp[v] = c.tag;
+        if (keep)
+            kept_min = dv < kept_min ? dv : kept_min;
+        int k = wave_alloc(c.near_cnt, move);
+        if (move)
+            c.near_q[k] = v;
+        k = wave_alloc(c.order_cnt, move);
+        if (move)
+            c.order[k] = v;
+        k = wave_alloc(c.kept_cnt, keep);
+        if (keep)
+            c.far_out[k] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rounds over the members of one band, for the path counts and for the
+// dependencies.  A member whose inputs are not all final yet is put on the
+// pending list for the next round; the member of least distance among the
+// pending ones always has final inputs, so every round makes progress.
+// ---------------------------------------------------------------------------
+struct RoundCtx {
+    const int32_t *items;
+    int len;
+    int worker, nworkers;
+    int lane_max;
+    int32_t s;          // the source
+    long long src_idx;  // its index in the source list (error reports)
+    bool first_round;
+    int32_t *pend_q;
+    int *pend_cnt;
+    unsigned long long *err; // [0] error bits, [1] first overflowing source index
+};
+
+__device__ __forceinline__ void report_sigma_overflow(unsigned long long *err, long long idx)
+{
+    atomicOr(&err[0], (unsigned long long)BC_ERRBIT_SIGMA);
+    atomicMin((long long *)&err[1], idx);
+}
+
+// Path counts (the counting rule of Alg. 2, evaluated by pulling): sigma[v]
+// is the sum of sigma[u] over arcs (u, v, w) with d[u] + w == d[v].  With
+// weights >= 1 every such u has d[u] < d[v], so it belongs to this band or
+// an earlier one.
+template <bool PACKED, int SCOPE>
+__device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
+                            uint64_t &dag)
+{
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        int32_t v = 0;
+        uint32_t beg = 0, end = 0;
+        if (valid) {
+            v = c.items[i];
+            beg = g.trow[v];
+            end = g.trow[v + 1];
+            if (c.first_round)
+                arcs += g.row[v + 1] - g.row[v];
+        }
+        const bool is_src = valid && v == c.s;
+        if (is_src)
+            store_f64<SCOPE>(&S.delta[v], -1.0); // sigma[s] = 1 was set at initialisation
+        const bool heavy = valid && !is_src && (end - beg) > (uint32_t)c.lane_max;
+        bool pend = false;
+        if (valid && !is_src && !heavy) {
+            const uint32_t dv = S.d[v];
+            uint64_t acc = 0;
+            bool ready = true, ovf = false;
+            uint32_t tight = 0;
+            for (uint32_t e = beg; e < end; ++e) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
+                if (S.d[u] + w == dv) {
+                    const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                    if (su == 0) {
+                        ready = false;
+                        break;
+                    }
+                    const uint64_t t = acc + su;
+                    ovf |= t < acc;
+                    acc = t;
+                    ++tight;
+                }
+            }
+            if (ready) {
+                if (ovf) {
+                    report_sigma_overflow(c.err, c.src_idx);
+                    acc = ~0ull; // stays non-zero so dependants do not wait forever
+                }
+                store_u64<SCOPE>(&S.sigma[v], acc);
+                store_f64<SCOPE>(&S.delta[v], -1.0);
+                dag += tight;
+            }
+            pend = !ready;
+        }
+        {
+            const int k = wave_alloc(c.pend_cnt, pend);
+            if (pend)
+                c.pend_q[k] = v;
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int32_t hv = __shfl(v, l);
+            const uint32_t hb = (uint32_t)__shfl((int)beg, l);
+            const uint32_t he = (uint32_t)__shfl((int)end, l);
+            const uint32_t dv = S.d[hv];
+            uint64_t acc = 0;
+            bool ready = true, ovf = false;
+            uint32_t tight = 0;
+            for (uint32_t e = hb + lane; e < he; e += WAVE) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
+                if (S.d[u] + w == dv) {
+                    const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                    if (su == 0) {
+                        ready = false;
+                        break;
+                    }
+                    const uint64_t t = acc + su;
+                    ovf |= t < acc;
+                    acc = t;
+                    ++tight;
+                }
+            }
+            const bool all_ready = __ballot(!ready) == 0;
+            acc = wave_sum_u64_checked(acc, ovf);
+            tight = wave_sum_u32(tight);
+            if (all_ready && lane == 0) {
+                if (ovf) {
+                    report_sigma_overflow(c.err, c.src_idx);
+                    acc = ~0ull;
+                }
+                store_u64<SCOPE>(&S.sigma[hv], acc);
+                store_f64<SCOPE>(&S.delta[hv], -1.0);
+                dag += tight;
+            }
+            const bool p = !all_ready && lane == 0;
+            const int k = wave_alloc(c.pend_cnt, p);
+            if (p)
+                c.pend_q[k] = hv;
+        }
+    }
+}
+
+// Dependencies (Sec. 2.1 recursion, Alg. 3): delta[v] is the sum over arcs
+// (v, u, w) with d[u] == d[v] + w of sigma[v] / sigma[u] * (1 + delta[u]);
+// every such u lies in this band or a later one.  A vertex other than the
+// source adds its dependency to the centrality: plainly into `bc` when the
+// caller owns it for this source (ATOMIC_BC false), with an FP64 atomic add
+// otherwise.
+template <bool PACKED, int SCOPE, bool ATOMIC_BC>
+__device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c, double *bc)
+{
+#pragma clang fp contract(off)
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        int32_t v = 0;
+        uint32_t beg = 0, end = 0;
+        if (valid) {
+            v = c.items[i];
+            beg = g.row[v];
+            end = g.row[v + 1];
+        }
+        const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
+        bool pend = false;
+        if (valid && !heavy) {
+            const uint32_t dv = S.d[v];
+            const double sv = (double)S.sigma[v];
+            double acc = 0.0;
+            bool ready = true;
+            for (uint32_t e = beg; e < end; ++e) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+                const uint32_t du = S.d[u];
+                if (du != BC_INF && du == dv + w) {
+                    const double dl = load_f64<SCOPE>(&S.delta[u]);
+                    if (dl < 0.0) {
+                        ready = false;
+                        break;
+                    }
+                    acc += sv / (double)S.sigma[u] * (1.0 + dl);
+                }
+            }
+            if (ready) {
+                store_f64<SCOPE>(&S.delta[v], acc);
+                if (v != c.s) {
+                    if (ATOMIC_BC)
+                        unsafeAtomicAdd(&bc[v], acc);
+                    else
+                        bc[v] += acc;
+                }
+            }
+            pend = !ready;
+        }
+        {
+            const int k = wave_alloc(c.pend_cnt, pend);
+            if (pend)
+                c.pend_q[k] = v;
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int32_t hv = __shfl(v, l);
+            const uint32_t hb = (uint32_t)__shfl((int)beg, l);
+            const uint32_t he = (uint32_t)__shfl((int)end, l);
+            const uint32_t dv = S.d[hv];
+            const double sv = (double)S.sigma[hv];
+            double acc = 0.0;
+            bool ready = true;
+            for (uint32_t e = hb + lane; e < he; e += WAVE) {
+                uint32_t u, w;
+                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+                const uint32_t du = S.d[u];
+                if (du != BC_INF && du == dv + w) {
+                    const double dl = load_f64<SCOPE>(&S.delta[u]);
+                    if (dl < 0.0) {
+                        ready = false;
+                        break;
+                    }
+                    acc += sv / (double)S.sigma[u] * (1.0 + dl);
+                }
+            }
+            const bool all_ready = __ballot(!ready) == 0;
+            acc = wave_sum_f64(acc);
+            if (all_ready && lane == 0) {
+                store_f64<SCOPE>(&S.delta[hv], acc);
+                if (hv != c.s) {
+                    if (ATOMIC_BC)
+                        unsafeAtomicAdd(&bc[hv], acc);
+                    else
+                        bc[hv] += acc;
+                }
+            }
+            const bool p = !all_ready && lane == 0;
+            const int k = wave_alloc(c.pend_cnt, p);
+            if (p)
+                c.pend_q[k] = hv;
+        }
+    }
+}

@@ -1,0 +1,105 @@
+"""The C-ABI library loads, exports what include/bc.h declares, and rejects
+bad input on the host before any device work (CPU only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1701_05975_amd import bc, graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(bc_[a-z_0-9]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["bc_create_graph", "bc_destroy_graph", "bc_compute", "bc_compute_device",
+                 "bc_result_bc", "bc_result_device_ptr", "bc_result_stats", "bc_destroy_result",
+                 "bc_source_state", "bc_last_error"]:
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports_every_declared_symbol(name):
+    lib = ctypes.CDLL(bc.LIB_PATH)
+    assert hasattr(lib, name), name
+
+
+def test_binding_uses_the_abi_names():
+    for name in declared_functions():
+        assert hasattr(bc, name), f"binding lacks {name}"
+
+
+def _err(fn):
+    with pytest.raises(bc.BCError) as ei:
+        fn()
+    return ei.value.status
+
+
+def test_validation_errors_before_device_work():
+    g = gg.path_graph(5)
+    assert _err(lambda: bc.bc_create_graph(0, [0], [], [])) == bc.BC_E_INVAL
+    bad_rp = g.row_ptr.copy()
+    bad_rp[2] = bad_rp[3] + 1
+    assert _err(lambda: bc.bc_create_graph(g.n, bad_rp, g.col, g.w)) == bc.BC_E_GRAPH
+    bad_col = g.col.copy()
+    bad_col[0] = 5
+    assert _err(lambda: bc.bc_create_graph(g.n, g.row_ptr, bad_col, g.w)) == bc.BC_E_GRAPH
+    bad_w = g.w.copy()
+    bad_w[1] = 0
+    assert _err(lambda: bc.bc_create_graph(g.n, g.row_ptr, g.col, bad_w)) == bc.BC_E_WEIGHT
+    # asymmetric weights on an undirected graph
+    asym = g.w.copy()
+    asym[0] = 7
+    assert _err(lambda: bc.bc_create_graph(g.n, g.row_ptr, g.col, asym)) == bc.BC_E_GRAPH
+    # ... accepted as directed (no GPU here, so the device step fails instead)
+    st = _err(lambda: bc.bc_create_graph(g.n, g.row_ptr, g.col, asym, bc.BC_DIRECTED))
+    assert st in (bc.BC_E_DEVICE, bc.BC_OK)
+    # distances that cannot fit int32
+    big = gg.path_graph(3, [2**30, 2**30])
+    assert _err(lambda: bc.bc_create_graph(big.n, big.row_ptr, big.col, big.w)) == bc.BC_E_DIST_OVERFLOW
+    with pytest.raises(bc.BCError) as ei:
+        bc.bc_create_graph(g.n, g.row_ptr, g.col, g.w, flags=8)
+    assert ei.value.status == bc.BC_E_INVAL
+    assert "flag" in ei.value.msg
+
+
+def test_last_error_is_thread_local_text():
+    g = gg.path_graph(4)
+    bad_w = g.w.copy()
+    bad_w[0] = -3
+    with pytest.raises(bc.BCError) as ei:
+        bc.bc_create_graph(g.n, g.row_ptr, g.col, bad_w)
+    assert "below 1" in ei.value.msg
+
+
+def test_algo_bytes_formula():
+    # arcs*(16+2*wb) + 72*reached + 24*dag + 20*n
+    assert bc.bc_algo_bytes(10, 2, 100, 9, 12) == 100 * 20 + 72 * 9 + 24 * 12 + 200
+
+
+def test_version_names_target():
+    assert "gfx950" in bc.bc_version()
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
+def test_no_device_is_reported_not_faked():
+    g = gg.path_graph(6)
+    with pytest.raises(bc.BCError) as ei:
+        bc.bc_create_graph(g.n, g.row_ptr, g.col, g.w)
+    assert ei.value.status == bc.BC_E_DEVICE

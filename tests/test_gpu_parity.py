@@ -1,0 +1,283 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Bar: distances and shortest-path counts bit-exact; per-source dependencies
+within 1e-12 relative and centralities within 1e-9 relative (exact zero
+where the oracle has zero).  All tests need an MI355X.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_05975_amd import bc, graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+INF64 = np.iinfo(np.int64).max
+INT32_MAX = 2**31 - 1
+
+# Option sets that change the schedule but never the result beyond rounding.
+OPTION_SETS = [
+    dict(),
+    dict(mode=bc.BC_MODE_PLAIN),
+    dict(delta=1),
+    dict(delta=1 << 28),
+    dict(lane_max_deg=1),
+    dict(lane_max_deg=1 << 20),
+    dict(wg_threads=1024),
+    dict(wg_threads=512, batch=3),
+    dict(accumulate=2),
+    dict(mode=bc.BC_MODE_PLAIN, delta=1, lane_max_deg=1),
+]
+
+
+def rel_close(got, want, tol):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    zero = want == 0
+    assert np.all(got[zero] == 0), np.nonzero(got[zero])[0][:10]
+    nz = ~zero
+    err = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
+    assert err.size == 0 or err.max() <= tol, (float(err.max()), int(np.argmax(err)))
+
+
+def check_state(g, G, s, **opts):
+    d, sg, dl = G.source_state(s, **opts)
+    od, osg, odl, nr = oracle.oracle_source_state(g, s)
+    od32 = np.where(od == INF64, INT32_MAX, od).astype(np.int32)
+    assert np.array_equal(d, od32), (s, np.nonzero(d != od32)[0][:10])
+    assert np.array_equal(sg, osg), (s, np.nonzero(sg != osg)[0][:10])
+    rel_close(dl, odl, 1e-12)
+
+
+def check_bc(g, G, sources, tol=1e-9, **opts):
+    got, st = G.bc(sources, **opts)
+    want = oracle.oracle_bc(g, np.arange(g.n) if sources is None else sources)
+    rel_close(got, want, tol)
+    return got, st
+
+
+# ------------------------------------------------------------------ small graphs
+
+def small_graphs():
+    out = []
+    for n, p, wl, wh, seed, directed in [
+        (1, 0.0, 1, 1, 0, False), (2, 1.0, 1, 5, 1, False), (7, 0.5, 1, 2, 2, False),
+        (63, 0.08, 1, 2, 3, False), (64, 0.1, 1, 3, 4, True), (65, 0.06, 1, 100, 5, False),
+        (200, 0.03, 1, 2, 6, True), (513, 0.012, 1, 9, 7, False), (1037, 0.006, 1, 1000, 8, True),
+    ]:
+        out.append(gg.random_graph(n, p, wl, wh, seed=seed, directed=directed))
+    return out
+
+
+@pytest.mark.parametrize("g", small_graphs(), ids=lambda g: f"{g.name}_s{g.meta['seed']}")
+def test_small_graphs_all_sources_every_option_set(g):
+    G = bc.Graph(g)
+    want = oracle.oracle_bc(g, np.arange(g.n))
+    srcs = sorted(set([0, g.n // 2, g.n - 1]))
+    for opts in OPTION_SETS:
+        got, st = G.bc(None, **opts)
+        rel_close(got, want, 1e-9)
+        assert st["sources"] == g.n
+        for s in srcs:
+            check_state(g, G, s, **opts)
+    G.close()
+
+
+def test_schedules_give_bit_identical_distances_and_counts():
+    g = gg.random_graph(700, 0.01, 1, 3, seed=42)
+    G = bc.Graph(g)
+    ref = None
+    for opts in OPTION_SETS:
+        for s in (0, 123, 699):
+            d, sg, _ = G.source_state(s, **opts)
+            if ref is None:
+                ref = {}
+            if s in ref:
+                assert np.array_equal(ref[s][0], d) and np.array_equal(ref[s][1], sg)
+            else:
+                ref[s] = (d, sg)
+
+
+# ------------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", [2, 3, 65, 300])
+def test_star_and_path_closed_forms(n):
+    rng = np.random.default_rng(n)
+    star = gg.star_graph(n, rng.integers(1, 50, size=n - 1))
+    G = bc.Graph(star)
+    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN)):
+        got, _ = G.bc(None, **opts)
+        assert got[0] == (n - 1) * (n - 2) and np.all(got[1:] == 0)
+    path = gg.path_graph(n, rng.integers(1, 1000, size=n - 1))
+    G = bc.Graph(path)
+    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN), dict(delta=1)):
+        got, _ = G.bc(None, **opts)
+        assert np.array_equal(got, [2 * i * (n - 1 - i) for i in range(n)])
+
+
+@pytest.mark.parametrize("n", [9, 10, 129])
+def test_cycle_and_complete(n):
+    G = bc.Graph(gg.cycle_graph(n))
+    got, _ = G.bc(None)
+    want = (n - 1) * (n - 3) / 4 if n % 2 else (n - 2) ** 2 / 4
+    rel_close(got, np.full(n, want), 1e-12)
+    G = bc.Graph(gg.complete_graph(40))
+    got, _ = G.bc(None)
+    assert np.all(got == 0)
+
+
+def test_unit_grid_binomial_counts():
+    g = gg.unit_grid(34, 34)
+    G = bc.Graph(g)
+    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN)):
+        d, sg, _ = G.source_state(0, **opts)
+        for i in (0, 5, 33):
+            for j in (0, 17, 33):
+                assert d[i * 34 + j] == i + j
+                assert int(sg[i * 34 + j]) == math.comb(i + j, i)
+
+
+def test_fig1a_example():
+    g = gg.undirected_from_edges(4, [0, 0, 1, 2], [1, 2, 2, 3], [1, 2, 1, 1])
+    G = bc.Graph(g)
+    for opts in OPTION_SETS:
+        _, sg, _ = G.source_state(0, **opts)
+        assert int(sg[3]) == 2
+
+
+# ------------------------------------------------------------------ overflow and edges
+
+def test_sigma_overflow_reported_with_first_source():
+    G = bc.Graph(gg.diamond_chain(63))
+    d, sg, _ = G.source_state(0)
+    assert int(sg[3 * 63]) == 2**63
+    G = bc.Graph(gg.diamond_chain(64))
+    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN)):
+        with pytest.raises(bc.BCError) as ei:
+            G.bc(np.array([1, 0, 2], np.int32), **opts)
+        assert ei.value.status == bc.BC_E_SIGMA_OVERFLOW
+        assert "index 1" in ei.value.msg
+    # the graph stays usable after the error
+    got, _ = G.bc(np.array([1], np.int32))
+    assert np.isfinite(got).all()
+
+
+def test_grid_35_overflows():
+    G = bc.Graph(gg.unit_grid(35, 35))
+    with pytest.raises(bc.BCError) as ei:
+        G.bc(np.array([0], np.int32))
+    assert ei.value.status == bc.BC_E_SIGMA_OVERFLOW
+
+
+def test_empty_and_degenerate_inputs():
+    g = gg.path_graph(5)
+    G = bc.Graph(g)
+    got, st = G.bc(np.zeros(0, np.int32))
+    assert np.all(got == 0) and st["sources"] == 0
+    got, _ = G.bc(np.zeros(0, np.int32), mode=bc.BC_MODE_PLAIN)
+    assert np.all(got == 0)
+    # repeated sources count once per occurrence
+    got, _ = G.bc(np.array([0, 0, 4], np.int32))
+    rel_close(got, oracle.oracle_bc(g, [0, 0, 4]), 1e-12)
+    # edgeless directed graph; single vertex
+    e = gg.csr_from_arcs(70, [], [], [], directed=True)
+    G = bc.Graph(e)
+    got, _ = G.bc(None)
+    assert np.all(got == 0)
+    d, sg, dl = G.source_state(3)
+    assert d[3] == 0 and sg[3] == 1 and dl[3] == 0 and np.all(d[np.arange(70) != 3] == INT32_MAX)
+    one = gg.csr_from_arcs(1, [], [], [], directed=False)
+    G = bc.Graph(one)
+    got, _ = G.bc(None)
+    assert got.tolist() == [0.0]
+    with pytest.raises(bc.BCError) as ei:
+        G.bc(np.array([1], np.int32))
+    assert ei.value.status == bc.BC_E_INVAL
+
+
+def test_directed_sinks_and_parallel_arcs():
+    # parallel equal-weight arcs are distinct shortest paths; sinks have no arcs
+    src = [0, 0, 1, 1, 2, 3, 3]
+    dst = [1, 1, 2, 3, 4, 4, 5]
+    w = [2, 2, 1, 1, 1, 1, 7]
+    g = gg.csr_from_arcs(6, src, dst, w, directed=True)
+    G = bc.Graph(g)
+    check_bc(g, G, None)
+    for s in range(6):
+        check_state(g, G, s)
+    d, sg, _ = G.source_state(0)
+    assert int(sg[1]) == 2 and int(sg[4]) == 4
+
+
+def test_device_entry_point_with_torch_tensors():
+    torch = pytest.importorskip("torch")
+    g = gg.ba_graph(3000, 3, 1, 50, seed=5)
+    G = bc.Graph(g)
+    srcs = np.arange(0, 3000, 7, dtype=np.int32)
+    s_dev = torch.from_numpy(srcs).cuda()
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = bc.bc_compute_device(G.handle, s_dev.data_ptr(), srcs.shape[0], out.data_ptr(),
+                              bc.make_options(stream=torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    rel_close(out.cpu().numpy(), oracle.oracle_bc(g, srcs), 1e-9)
+    assert st.sources == srcs.shape[0] and st.reached > 0
+
+
+# ------------------------------------------------------------------ configurations
+
+def test_config_er1000_all_sources():
+    g = gg.config_graph("er1000")
+    G = bc.Graph(g)
+    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN), dict(accumulate=2)):
+        check_bc(g, G, None, **opts)
+    for s in (0, 1, 500, 999):
+        check_state(g, G, s)
+
+
+def test_config_ba100k_parity_sources():
+    g = gg.config_graph("ba100k")
+    G = bc.Graph(g)
+    srcs = gg.config_sources("ba100k", g, parity=True)
+    check_bc(g, G, srcs)
+    for s in srcs[:3]:
+        check_state(g, G, int(s))
+        check_state(g, G, int(s), mode=bc.BC_MODE_PLAIN)
+
+
+def test_config_ba100k_full_launch_linearity():
+    """All 100k sources in the benchmark's launch configuration: BC over all
+    sources equals the sum over two halves, and sampled sources' states in
+    that configuration match the oracle."""
+    g = gg.config_graph("ba100k")
+    G = bc.Graph(g)
+    allsrc = np.arange(g.n, dtype=np.int32)
+    full, st = G.bc(allsrc)
+    a, _ = G.bc(allsrc[: g.n // 2])
+    b, _ = G.bc(allsrc[g.n // 2:])
+    assert np.all(np.isfinite(full)) and np.all(full >= 0)
+    rel_close(full, a + b, 1e-9)
+    assert st["reached"] == g.n * g.n  # connected graph
+    for s in (0, 77_777, 99_999):
+        check_state(g, G, s)
+
+
+def test_config_grid_sampled_sources():
+    g = gg.config_graph("grid1000")
+    G = bc.Graph(g)
+    srcs = gg.config_sources("grid1000", g)[:16]
+    check_bc(g, G, srcs)
+    for s in srcs[:2]:
+        check_state(g, G, int(s))
+
+
+@pytest.mark.slow
+def test_config_rmat22_sampled_sources():
+    g = gg.config_graph("rmat22")
+    G = bc.Graph(g)
+    srcs = gg.config_sources("rmat22", g)[:2]
+    check_bc(g, G, srcs)
+    check_state(g, G, int(srcs[0]))
