@@ -195,6 +195,68 @@ bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t
 double bc_algo_bytes(int32_t n, int32_t weight_bytes, int64_t arcs, int64_t reached,
                      int64_t dag_arcs);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * The server owns one scheduler thread and all device work of its requests.
+ * Graphs are caller-owned bc_graph handles that stay resident; per graph the
+ * server keeps a few sweep contexts (state slabs, a stream).  A sweep is one
+ * bounded launch of the batched form over sources taken from the admitted
+ * requests of that graph, oldest request first, each source adding its
+ * dependencies into its own request's result (FP64 atomics).  A request that
+ * arrives while others run is admitted, first come first served, as soon as
+ * the free device memory and the server's result budget allow its result
+ * buffer (8 n bytes), and its sources join the next sweep of its graph.
+ * Results equal bc_compute over the same sources up to floating-point
+ * summation order.  A failing source (path-count overflow) fails only its own
+ * request.
+ * ------------------------------------------------------------------------ */
+typedef struct bc_server bc_server;
+
+typedef struct {
+    int64_t result_budget_bytes;  /* device bytes that admitted, unretrieved results may hold;
+                                     0 = a quarter of the free memory at creation */
+    int64_t slab_bytes_per_sweep; /* state-slab memory of one sweep context; 0 = 4 GiB */
+    int32_t max_active;           /* admitted, unfinished requests; 0 = 64 */
+    int32_t sweeps_per_graph;     /* concurrent sweeps per graph; 0 = 2 */
+    int32_t slots_per_sweep;      /* sources in flight per sweep; 0 = fill the GPU within the
+                                     slab memory */
+    int32_t items_per_sweep;      /* sources per sweep; 0 = twice the slots */
+    bc_options compute;           /* delta, lane_max_deg and wg_threads of the sweeps; 0 fields
+                                     take the graph's autotuned (else default) values; mode,
+                                     batch, accumulate and stream are ignored */
+} bc_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, failed, waiting, active;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* arrival -> completion of completed requests */
+    double queue_ms_sum;                    /* total arrival -> admission time */
+    double gteps;          /* sum of k*m over retrieved requests / (last completion - first
+                              arrival) */
+    int64_t sweeps;        /* sweep launches so far */
+    int64_t device_bytes_in_use; /* result bytes held by admitted, unretrieved requests */
+} bc_server_stats;
+
+/* Start a server on the current device (opts may be NULL for defaults). */
+bc_status bc_server_create(const bc_server_opts *opts, bc_server **out);
+/*
+ * Queue a request: betweenness of graph g over sources[k] (host array, copied;
+ * k = 0 allowed).  Returns at once with a ticket.  BC_E_BUSY if the result can
+ * never fit the server's budget; BC_E_INVAL for out-of-range sources.
+ */
+bc_status bc_server_submit(bc_server *sv, bc_graph *g, const int32_t *sources, int64_t k,
+                           uint64_t *ticket);
+/*
+ * Wait for a request (timeout_us < 0 waits forever) and take its result; the
+ * result handle owns the device buffer (release with bc_destroy_result) and its
+ * stats report ms = arrival-to-completion latency.  BC_E_TIMEOUT leaves the
+ * request queued; a failed request returns its error and is discarded.
+ */
+bc_status bc_server_wait(bc_server *sv, uint64_t ticket, int64_t timeout_us, bc_result **out);
+bc_status bc_server_get_stats(bc_server *sv, bc_server_stats *stats);
+/* Stop the scheduler after the sweeps in flight, free every unretrieved result. */
+bc_status bc_server_destroy(bc_server *sv);
+
 const char *bc_last_error(void);
 
 /* Library version string. */

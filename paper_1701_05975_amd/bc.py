@@ -75,6 +75,26 @@ class bc_graph_info(ctypes.Structure):
                 ("packed_arcs", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
+class bc_server_opts(ctypes.Structure):
+    _fields_ = [("result_budget_bytes", ctypes.c_int64), ("slab_bytes_per_sweep", ctypes.c_int64),
+                ("max_active", ctypes.c_int32), ("sweeps_per_graph", ctypes.c_int32),
+                ("slots_per_sweep", ctypes.c_int32), ("items_per_sweep", ctypes.c_int32),
+                ("compute", bc_options)]
+
+
+class bc_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("waiting", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("queue_ms_sum", ctypes.c_double),
+                ("gteps", ctypes.c_double), ("sweeps", ctypes.c_int64),
+                ("device_bytes_in_use", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def _load():
     # torch ships its own HIP runtime with the same soname as the system one;
     # loading torch first makes this library bind to that single runtime, so
@@ -100,6 +120,11 @@ def _load():
         "bc_destroy_result": ([P], ctypes.c_int),
         "bc_source_state": ([P, i32, ctypes.POINTER(bc_options), P, P, P], ctypes.c_int),
         "bc_algo_bytes": ([i32, i32, i64, i64, i64], ctypes.c_double),
+        "bc_server_create": ([ctypes.POINTER(bc_server_opts), ctypes.POINTER(P)], ctypes.c_int),
+        "bc_server_submit": ([P, P, P, i64, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "bc_server_wait": ([P, ctypes.c_uint64, i64, ctypes.POINTER(P)], ctypes.c_int),
+        "bc_server_get_stats": ([P, ctypes.POINTER(bc_server_stats)], ctypes.c_int),
+        "bc_server_destroy": ([P], ctypes.c_int),
         "bc_last_error": ([], ctypes.c_char_p),
         "bc_version": ([], ctypes.c_char_p),
     }
@@ -259,3 +284,82 @@ class Graph:
 
 def bc_last_error() -> str:
     return _lib.bc_last_error().decode()
+
+
+# --------------------------------------------------------------------------- serving
+
+def bc_server_create(opts: bc_server_opts | None = None):
+    out = ctypes.c_void_p()
+    _check(_lib.bc_server_create(ctypes.byref(opts) if opts is not None else None,
+                                 ctypes.byref(out)))
+    return out
+
+
+def bc_server_submit(sv, g, sources) -> int:
+    s = np.ascontiguousarray(sources, dtype=np.int32)
+    t = ctypes.c_uint64()
+    _check(_lib.bc_server_submit(sv, g, _ptr(s) if s.size else None, int(s.shape[0]),
+                                 ctypes.byref(t)))
+    return t.value
+
+
+def bc_server_wait(sv, ticket: int, timeout_us: int = -1):
+    out = ctypes.c_void_p()
+    _check(_lib.bc_server_wait(sv, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(out)))
+    return out
+
+
+def bc_server_get_stats(sv) -> bc_server_stats:
+    st = bc_server_stats()
+    _check(_lib.bc_server_get_stats(sv, ctypes.byref(st)))
+    return st
+
+
+def bc_server_destroy(sv) -> None:
+    _check(_lib.bc_server_destroy(sv))
+
+
+def make_server_opts(result_budget_bytes=0, slab_bytes_per_sweep=0, max_active=0,
+                     sweeps_per_graph=0, slots_per_sweep=0, items_per_sweep=0,
+                     **compute) -> bc_server_opts:
+    o = bc_server_opts()
+    o.result_budget_bytes = result_budget_bytes
+    o.slab_bytes_per_sweep = slab_bytes_per_sweep
+    o.max_active = max_active
+    o.sweeps_per_graph = sweeps_per_graph
+    o.slots_per_sweep = slots_per_sweep
+    o.items_per_sweep = items_per_sweep
+    o.compute = make_options(**compute)
+    return o
+
+
+class Server:
+    """Owning wrapper of a bc_server handle."""
+
+    def __init__(self, **opts):
+        self.handle = bc_server_create(make_server_opts(**opts))
+
+    def submit(self, graph: "Graph", sources) -> int:
+        return bc_server_submit(self.handle, graph.handle, sources)
+
+    def wait(self, ticket: int, n: int, timeout_us: int = -1):
+        """(bc float64[n], latency ms) of a finished request."""
+        r = bc_server_wait(self.handle, ticket, timeout_us)
+        try:
+            return bc_result_bc(r, n), bc_result_stats(r).ms
+        finally:
+            bc_destroy_result(r)
+
+    def stats(self) -> dict:
+        return bc_server_get_stats(self.handle).as_dict()
+
+    def close(self):
+        if self.handle:
+            bc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

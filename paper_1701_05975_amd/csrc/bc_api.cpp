@@ -45,6 +45,8 @@ void hip_check(hipError_t e, const char *what)
     throw bc_error(s, "%s: %s", what, hipGetErrorString(e));
 }
 
+void bc_set_last_error(const std::string &msg) { g_last_error = msg; }
+
 bc_status bc_fail(const bc_error &e)
 {
     g_last_error = e.msg;
@@ -517,6 +519,8 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         DevCounters *c = (DevCounters *)g->ctl.p;
         a.next_src = &c->next_src;
         a.bc_out = bc_dev;
+        a.item_out = nullptr;
+        a.item_err = nullptr;
         a.delta = (uint32_t)r.delta;
         a.lane_max = r.lane_max;
         a.stats = &c->stats;

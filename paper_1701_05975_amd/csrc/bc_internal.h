@@ -15,6 +15,7 @@ struct bc_error {
 };
 
 void hip_check(hipError_t e, const char *what);
+void bc_set_last_error(const std::string &msg);
 
 struct DevBuf {
     void *p = nullptr;

@@ -15,6 +15,8 @@ struct BatchArgs {
     long long k;
     unsigned long long *next_src; // device counter handing out sources
     double *bc_out;               // output (atomic accumulation mode)
+    double *const *item_out;      // optional: output of each source-list entry (serving)
+    unsigned int *item_err;       // optional: set to 1 for each entry whose counts overflowed
     uint32_t delta;               // band width
     int lane_max;
     DevStats *stats;

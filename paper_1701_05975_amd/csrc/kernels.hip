@@ -59,6 +59,7 @@ __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const
         rc.pend_q = which ? S.qb : S.qa;
         rc.pend_cnt = &C.pend_cnt;
         rc.err = a.err;
+        rc.item_err = a.item_err;
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE>(g, S, rc, st_arcs, st_dag);
         else
@@ -91,7 +92,6 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
     const DevGraph &g = a.g;
     const int n = g.n;
     Slab S = slab_at(a.slab_base, a.L, blockIdx.x);
-    double *bc = ATOMIC_BC ? a.bc_out : S.bcp;
     if (!ATOMIC_BC)
         for (int v = tid; v < n; v += NT)
             S.bcp[v] = 0.0;
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         if (idx >= a.k)
             break;
         const int32_t s = a.sources[idx];
+        double *bc = ATOMIC_BC ? (a.item_out ? a.item_out[idx] : a.bc_out) : S.bcp;
 
         // Queue tags only grow; restart them long before they could wrap.
         if (C.gen > (1 << 30)) {
@@ -500,6 +501,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.pend_q = first ? S.qa : (c->pcur ? S.qa : S.qb);
         rc.pend_cnt = &c->pend_cnt;
         rc.err = a.err;
+        rc.item_err = nullptr;
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
             sigma_round<PACKED, AG_SCOPE>(g, S, rc, arcs, dag);

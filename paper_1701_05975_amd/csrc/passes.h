@@ -217,12 +217,15 @@ struct RoundCtx {
     int32_t *pend_q;
     int *pend_cnt;
     unsigned long long *err; // [0] error bits, [1] first overflowing source index
+    unsigned int *item_err;  // optional per-source-entry overflow flags
 };
 
-__device__ __forceinline__ void report_sigma_overflow(unsigned long long *err, long long idx)
+__device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 {
-    atomicOr(&err[0], (unsigned long long)BC_ERRBIT_SIGMA);
-    atomicMin((long long *)&err[1], idx);
+    atomicOr(&c.err[0], (unsigned long long)BC_ERRBIT_SIGMA);
+    atomicMin((long long *)&c.err[1], c.src_idx);
+    if (c.item_err)
+        c.item_err[c.src_idx] = 1u;
 }
 
 // Path counts (the counting rule of Alg. 2, evaluated by pulling): sigma[v]
@@ -273,7 +276,7 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             }
             if (ready) {
                 if (ovf) {
-                    report_sigma_overflow(c.err, c.src_idx);
+                    report_sigma_overflow(c);
                     acc = ~0ull; // stays non-zero so dependants do not wait forever
                 }
                 store_u64<SCOPE>(&S.sigma[v], acc);
@@ -318,7 +321,7 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             tight = wave_sum_u32(tight);
             if (all_ready && lane == 0) {
                 if (ovf) {
-                    report_sigma_overflow(c.err, c.src_idx);
+                    report_sigma_overflow(c);
                     acc = ~0ull;
                 }
                 store_u64<SCOPE>(&S.sigma[hv], acc);

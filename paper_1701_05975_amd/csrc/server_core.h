@@ -1,0 +1,266 @@
+// server_core.h -- admission and scheduling policy of the serving form.
+//
+// Header-only and free of HIP so that the policy can be exercised on the CPU
+// with a fake executor and a fake clock.  The executor runs "sweeps": one
+// bounded launch of the batched kernel over a list of (source, request)
+// items of one graph.  Continuous batching: a request that arrives while
+// others run is admitted as soon as memory and request slots allow, and its
+// sources join the next sweep of its graph alongside the sources of earlier
+// requests; sweeps of different graphs (and several sweeps of one graph)
+// run concurrently.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+namespace bcserve {
+
+enum class ReqPhase { Waiting, Active, Done, Failed };
+
+struct Request {
+    uint64_t ticket = 0;
+    int graph = 0;                 // executor-side graph index
+    std::vector<int32_t> sources;
+    int64_t next_item = 0;         // next source to hand to a sweep
+    int64_t done_items = 0;        // sources whose sweeps have finished
+    int64_t inflight_items = 0;
+    size_t bytes = 0;              // device bytes held while admitted (result buffer)
+    double t_arrival = 0, t_admit = 0, t_done = 0;
+    ReqPhase phase = ReqPhase::Waiting;
+    int status = 0;                // 0 ok, else a bc_status of the failure
+    int64_t first_bad = -1;        // index (in this request's source list) of an overflow
+    void *out = nullptr;           // executor-owned result buffer
+    bool retrieved = false;
+};
+
+struct SweepItem {
+    int32_t source;
+    uint64_t ticket;
+    int64_t index_in_request;
+};
+
+struct Policy {
+    size_t budget_bytes = 0;       // device bytes the requests may hold at once
+    int max_active = 64;           // admitted, unfinished requests
+    int max_items_per_sweep = 1024;
+};
+
+// Executor interface:
+//   int  free_contexts(int graph)                 sweeps that could start now
+//   int  max_items(int graph)                     sources one sweep of the graph can take
+//   bool alloc_result(Request&)                   device buffer for the result (zeroed)
+//   void free_result(Request&)
+//   void launch(int graph, const std::vector<SweepItem>&)
+//   void poll(std::vector<Finished>&)             sweeps finished since last poll
+struct Finished {
+    int graph;
+    std::vector<SweepItem> items;
+    int err_status = 0;              // bc_status of a sweep-wide device error, 0 if none
+    std::vector<uint8_t> item_fail;  // per item: 1 if its path counts overflowed
+    int item_status = 0;             // bc_status reported for a failed item
+};
+
+template <class Exec> class Scheduler {
+  public:
+    Scheduler(Exec &ex, Policy p) : ex_(ex), pol_(p) {}
+
+    uint64_t submit(int graph, const int32_t *src, int64_t k, size_t result_bytes, double now)
+    {
+        auto r = std::make_shared<Request>();
+        r->ticket = ++last_ticket_;
+        r->graph = graph;
+        r->sources.assign(src, src + k);
+        r->bytes = result_bytes;
+        r->t_arrival = now;
+        reqs_[r->ticket] = r;
+        waiting_.push_back(r->ticket);
+        ++submitted_;
+        return r->ticket;
+    }
+
+    // One scheduling step: collect finished sweeps, admit, dispatch.
+    // Returns true if anything changed.
+    bool step(double now)
+    {
+        bool changed = collect(now);
+        changed |= admit(now);
+        changed |= dispatch();
+        return changed;
+    }
+
+    std::shared_ptr<Request> find(uint64_t t) const
+    {
+        auto it = reqs_.find(t);
+        return it == reqs_.end() ? nullptr : it->second;
+    }
+
+    // The caller took ownership of the result (or dropped it): the memory
+    // it held is no longer charged to the budget.
+    void release(uint64_t t)
+    {
+        auto r = find(t);
+        if (!r)
+            return;
+        if (r->phase == ReqPhase::Done || r->phase == ReqPhase::Failed) {
+            if (!r->retrieved) {
+                r->retrieved = true;
+                in_use_ -= std::min(in_use_, r->bytes);
+            }
+            finished_.push_back(*r);
+            reqs_.erase(t);
+        }
+    }
+
+    size_t in_use() const { return in_use_; }
+    int active() const { return active_; }
+    size_t waiting() const { return waiting_.size(); }
+    int64_t submitted() const { return submitted_; }
+    const std::vector<Request> &finished_log() const { return finished_; }
+    bool idle() const { return waiting_.empty() && active_ == 0 && inflight_sweeps_ == 0; }
+
+    template <class F> void for_each_request(F f) const
+    {
+        for (auto &kv : reqs_)
+            f(*kv.second);
+    }
+
+  private:
+    bool collect(double now)
+    {
+        std::vector<Finished> fin;
+        ex_.poll(fin);
+        for (auto &f : fin) {
+            --inflight_sweeps_;
+            for (size_t i = 0; i < f.items.size(); ++i) {
+                auto r = find(f.items[i].ticket);
+                if (!r)
+                    continue;
+                r->inflight_items -= 1;
+                r->done_items += 1;
+                const bool failed = i < f.item_fail.size() && f.item_fail[i];
+                if (failed && (r->first_bad < 0 ||
+                               f.items[i].index_in_request < r->first_bad)) {
+                    r->status = f.item_status;
+                    r->first_bad = f.items[i].index_in_request;
+                }
+                if (f.err_status && r->status == 0)
+                    r->status = f.err_status;
+            }
+            for (auto &it : f.items) {
+                auto r = find(it.ticket);
+                if (r && r->phase == ReqPhase::Active &&
+                    r->done_items == (int64_t)r->sources.size())
+                    finish(*r, now);
+            }
+        }
+        return !fin.empty();
+    }
+
+    void finish(Request &r, double now)
+    {
+        r.phase = r.status ? ReqPhase::Failed : ReqPhase::Done;
+        r.t_done = now;
+        --active_;
+    }
+
+    bool admit(double now)
+    {
+        bool changed = false;
+        while (!waiting_.empty()) {
+            auto r = find(waiting_.front());
+            if (!r) {
+                waiting_.pop_front();
+                continue;
+            }
+            if (active_ >= pol_.max_active)
+                break;
+            if (in_use_ + r->bytes > pol_.budget_bytes)
+                break; // FIFO: the head waits for memory, later requests wait behind it
+            if (!ex_.alloc_result(*r))
+                break;
+            waiting_.pop_front();
+            in_use_ += r->bytes;
+            r->phase = ReqPhase::Active;
+            r->t_admit = now;
+            ++active_;
+            order_.push_back(r->ticket);
+            changed = true;
+            if (r->sources.empty())
+                finish(*r, now);
+        }
+        return changed;
+    }
+
+    bool dispatch()
+    {
+        bool changed = false;
+        // graphs with pending items, oldest request first
+        std::vector<int> graphs;
+        for (auto it = order_.begin(); it != order_.end();) {
+            auto r = find(*it);
+            if (!r || r->phase != ReqPhase::Active ||
+                r->next_item == (int64_t)r->sources.size()) {
+                it = order_.erase(it);
+                continue;
+            }
+            if (std::find(graphs.begin(), graphs.end(), r->graph) == graphs.end())
+                graphs.push_back(r->graph);
+            ++it;
+        }
+        for (int gidx : graphs) {
+            const int cap = std::min(pol_.max_items_per_sweep, ex_.max_items(gidx));
+            while (ex_.free_contexts(gidx) > 0) {
+                std::vector<SweepItem> items;
+                for (uint64_t t : order_) {
+                    auto r = find(t);
+                    if (!r || r->graph != gidx)
+                        continue;
+                    while (r->next_item < (int64_t)r->sources.size() &&
+                           (int)items.size() < cap) {
+                        items.push_back({r->sources[(size_t)r->next_item], r->ticket,
+                                         r->next_item});
+                        r->next_item += 1;
+                        r->inflight_items += 1;
+                    }
+                    if ((int)items.size() >= cap)
+                        break;
+                }
+                if (items.empty())
+                    break;
+                ex_.launch(gidx, items);
+                ++inflight_sweeps_;
+                changed = true;
+            }
+        }
+        return changed;
+    }
+
+    Exec &ex_;
+    Policy pol_;
+    std::map<uint64_t, std::shared_ptr<Request>> reqs_;
+    std::deque<uint64_t> waiting_;
+    std::deque<uint64_t> order_;
+    std::vector<Request> finished_;
+    uint64_t last_ticket_ = 0;
+    size_t in_use_ = 0;
+    int active_ = 0;
+    int inflight_sweeps_ = 0;
+    int64_t submitted_ = 0;
+};
+
+// Percentile of a sample (nearest rank), 0 for an empty sample.
+inline double percentile(std::vector<double> v, double p)
+{
+    if (v.empty())
+        return 0.0;
+    std::sort(v.begin(), v.end());
+    size_t rank = (size_t)std::max(1.0, std::ceil(p / 100.0 * (double)v.size()));
+    return v[std::min(rank, v.size()) - 1];
+}
+
+} // namespace bcserve
