@@ -33,7 +33,111 @@ WORKLOADS = {
                 "k=1024 sampled sources",
     "rmat22": "directed R-MAT scale 22 (a,b,c=.57,.19,.19; self-loops/duplicates dropped), "
               "w uniform [1,255], k=1024 sampled sources",
+    "serving": "8 resident graphs (ER n=10k/500k deg 8 w[1,100]; BA n=50k/1M m=5 w[1,1000]; "
+               "grid 100x100/1414x1414 -2% w[1,255]; R-MAT scale 14/21 w[1,255]); Poisson "
+               "arrivals; each request k-sampled BC, k log-uniform in [64,4096]",
 }
+
+
+def serving_graphs():
+    from paper_1701_05975_amd import graphgen as gg
+    return [
+        gg.er_graph(10_000, 40_000, 1, 100, seed=101),
+        gg.er_graph(500_000, 2_000_000, 1, 100, seed=102),
+        gg.ba_graph(50_000, 5, 1, 1000, seed=103),
+        gg.ba_graph(1_000_000, 5, 1, 1000, seed=104),
+        gg.grid_graph(100, 100, 396, 1, 255, seed=105),
+        gg.grid_graph(1414, 1414, 79_941, 1, 255, seed=106),
+        gg.rmat_graph(14, 16 << 14, .57, .19, .19, 1, 255, seed=107),
+        gg.rmat_graph(21, 16 << 21, .57, .19, .19, 1, 255, seed=108),
+    ]
+
+
+def run_serving(args):
+    """Open-loop serving run: Poisson arrivals at a fixed rate, latency from
+    arrival to completion measured inside the server."""
+    import torch  # noqa: F401  (one HIP runtime for the process)
+    from paper_1701_05975_amd import bc, graphgen as gg
+
+    t0 = time.perf_counter()
+    graphs = serving_graphs()
+    print(f"# generated 8 graphs in {time.perf_counter() - t0:.1f}s: " +
+          ", ".join(f"{g.name}(n={g.n},m={g.m})" for g in graphs), file=sys.stderr, flush=True)
+    G = [bc.Graph(g) for g in graphs]
+    print("# graphs resident on the device", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(200)
+    nreq = args.requests
+    reqs = []
+    for i in range(nreq):
+        gi = int(rng.integers(0, len(graphs)))
+        k = int(np.floor(np.exp(rng.uniform(np.log(64), np.log(4096)))))
+        reqs.append((gi, gg.sample_sources(graphs[gi], k, seed=10_000 + i)))
+    work = np.array([len(s) * graphs[gi].m for gi, s in reqs], dtype=np.float64)
+    sv = bc.Server()
+    # capacity estimate: the warm-up requests served back to back (closed loop)
+    warm = args.serve_warmup
+    tw = time.perf_counter()
+    ts = [sv.submit(G[gi], s) for gi, s in reqs[:warm]]
+    for (gi, s), t in zip(reqs[:warm], ts):
+        _, ms = sv.wait(t, graphs[gi].n)
+        print(f"# warm-up request: graph {graphs[gi].name} k={len(s)} {ms:.1f} ms",
+              file=sys.stderr, flush=True)
+    cap = work[:warm].sum() / (time.perf_counter() - tw)  # edges*sources per second
+    lam = args.rate if args.rate > 0 else args.load * cap / work.mean()
+    print(f"# warm-up: {warm} requests, capacity ~{cap / 1e9:.2f} GTEPS; "
+          f"arrival rate {lam:.3f} req/s", file=sys.stderr, flush=True)
+    sv.close()
+    sv = bc.Server()
+    gaps = np.random.default_rng(201).exponential(1.0 / lam, size=nreq)
+    start = time.perf_counter()
+    arrivals = start + np.cumsum(gaps)
+    tickets = []
+    for (gi, s), ta in zip(reqs, arrivals):
+        dt = ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(sv.submit(G[gi], s))
+    lat = []
+    results = {}
+    for i, ((gi, s), t) in enumerate(zip(reqs, tickets)):
+        out, ms = sv.wait(t, graphs[gi].n)
+        lat.append(ms)
+        print(f"# request {i}: graph {graphs[gi].name} k={len(s)} latency {ms:.1f} ms",
+              file=sys.stderr, flush=True)
+        if i in (1, nreq // 2, nreq - 1):
+            results[i] = out
+    st = sv.stats()
+    sv.close()
+    # each spot-checked result must equal the same request computed alone
+    worst = 0.0
+    for i, out in results.items():
+        gi, s = reqs[i]
+        alone, _ = G[gi].bc(s)
+        nz = alone != 0
+        assert np.all(out[~nz] == 0)
+        if nz.any():
+            worst = max(worst, float(np.max(np.abs(out[nz] - alone[nz]) / np.abs(alone[nz]))))
+    assert worst <= 1e-9, worst
+    lat = np.array(lat)
+    rec = {
+        "metric": "served BC request latency p50/p99 at a fixed Poisson rate; aggregate GTEPS",
+        "value": round(float(np.percentile(lat, 50)), 2),
+        "unit": "ms (p50)",
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "mean_ms": round(float(lat.mean()), 2),
+        "gteps": round(st["gteps"], 4),
+        "n_gpus": 1,
+        "requests": nreq,
+        "rate_req_per_s": round(lam, 4),
+        "higher_is_better": False,
+        "sweeps": st["sweeps"],
+        "mix_vs_alone_max_rel_err": worst,
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": f"serving: {WORKLOADS['serving']}", "load": args.load,
+                   "graphs": [f"{g.name} n={g.n} m={g.m}" for g in graphs]},
+    }
+    print(json.dumps(rec), flush=True)
 
 HBM_PEAK_GBS = 8000.0
 
@@ -122,6 +226,10 @@ def main():
     ap.add_argument("--lane-max", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
+    ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
+    ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: fixed arrival rate")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -131,6 +239,9 @@ def main():
         sys.exit(2)
 
     ensure_built()
+    if args.config == "serving":
+        run_serving(args)
+        return
     import torch
 
     from paper_1701_05975_amd import bc, graphgen as gg

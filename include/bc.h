@@ -56,8 +56,11 @@ typedef enum {
 } bc_status;
 
 /* bc_create_graph flags */
-#define BC_DIRECTED 1u /* arcs are one-way; without it every arc must have a reverse arc
-                          of equal weight (checked) */
+#define BC_DIRECTED 1u   /* arcs are one-way; without it every arc must have a reverse arc
+                            of equal weight (checked) */
+#define BC_KEEP_ORDER 2u /* keep the caller's vertex numbering on the device; by default a
+                            graph whose in-degrees are skewed is renumbered internally by
+                            decreasing in-degree (results are always in the caller's ids) */
 
 typedef struct bc_graph bc_graph;
 typedef struct bc_result bc_result;
@@ -90,6 +93,7 @@ typedef struct {
     int32_t w_max;
     int32_t max_out_degree;
     int32_t packed_arcs; /* 1 when arc head and weight share one 32-bit word on the device */
+    int32_t renumbered;  /* 1 when the device numbering is by decreasing in-degree */
     int64_t device_bytes; /* graph bytes resident on the device */
 } bc_graph_info;
 
@@ -118,7 +122,8 @@ typedef struct {
     int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best */
     int32_t accumulate;   /* 0 = default, 1 = per-slot partial sums + reduction,
                              2 = device-wide FP64 atomic adds into the output */
-    int32_t reserved;
+    int32_t lds_vertices; /* batched: distances of this many highest in-degree vertices are
+                             kept in LDS per source; 0 = as many as fit, -1 = none */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -137,7 +142,7 @@ typedef struct {
     double algo_bytes;        /* algorithmic bytes of the work (see bc_algo_bytes) */
     double kernel_ms;         /* device time of the main kernel launches alone (HIP events) */
     int64_t kernel_launches;  /* number of main kernel launches timed in kernel_ms */
-    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate;
+    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices;
 } bc_stats;
 
 /*
@@ -160,7 +165,8 @@ bc_status bc_compute(bc_graph *g, const int32_t *sources, int64_t k, const bc_op
  * bc_compute_device -- as bc_compute, for data already on the device.
  *
  * sources_dev[k] is a device int32 array; bc_dev[n] is a device double array
- * that receives the result (overwritten).  The call enqueues the work on
+ * that receives the result (overwritten).  Sources are range-checked on the
+ * device; an out-of-range entry yields BC_E_INVAL (bc_dev is then not valid).  The call enqueues the work on
  * opt->stream (or the graph's stream) and waits for it; stats may be NULL.
  * No host<->device transfer of inputs or outputs takes place.
  */
@@ -216,7 +222,8 @@ typedef struct bc_server bc_server;
 typedef struct {
     int64_t result_budget_bytes;  /* device bytes that admitted, unretrieved results may hold;
                                      0 = a quarter of the free memory at creation */
-    int64_t slab_bytes_per_sweep; /* state-slab memory of one sweep context; 0 = 4 GiB */
+    int64_t slab_bytes_per_sweep; /* state-slab memory of one sweep context; 0 = 1/16 of the
+                                     free memory at creation */
     int32_t max_active;           /* admitted, unfinished requests; 0 = 64 */
     int32_t sweeps_per_graph;     /* concurrent sweeps per graph; 0 = 2 */
     int32_t slots_per_sweep;      /* sources in flight per sweep; 0 = fill the GPU within the

@@ -34,6 +34,7 @@ STATUS_NAMES = {
 }
 
 BC_DIRECTED = 1
+BC_KEEP_ORDER = 2
 BC_MODE_AUTO, BC_MODE_BATCHED, BC_MODE_PLAIN = 0, 1, 2
 
 INT32_MAX = 2**31 - 1
@@ -50,7 +51,7 @@ class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("lds_vertices", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class bc_stats(ctypes.Structure):
@@ -63,7 +64,7 @@ class bc_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
-                ("accumulate", ctypes.c_int32)]
+                ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -72,7 +73,8 @@ class bc_stats(ctypes.Structure):
 class bc_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("directed", ctypes.c_int32),
                 ("w_max", ctypes.c_int32), ("max_out_degree", ctypes.c_int32),
-                ("packed_arcs", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("packed_arcs", ctypes.c_int32), ("renumbered", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
 
 
 class bc_server_opts(ctypes.Structure):
@@ -152,10 +154,11 @@ def _ptr(a: np.ndarray):
 
 
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
-                 accumulate=0, stream=None) -> bc_options:
+                 accumulate=0, lds_vertices=0, stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
     o.lane_max_deg, o.wg_threads, o.autotune, o.accumulate = lane_max_deg, wg_threads, autotune, accumulate
+    o.lds_vertices = lds_vertices
     o.stream = stream
     return o
 
@@ -248,11 +251,11 @@ def bc_version() -> str:
 class Graph:
     """Owning wrapper of a bc_graph handle built from a CSR graph object."""
 
-    def __init__(self, csr):
+    def __init__(self, csr, keep_order: bool = False):
         self.n = int(csr.n)
         self.m = int(csr.m)
         self.csr = csr
-        flags = BC_DIRECTED if csr.directed else 0
+        flags = (BC_DIRECTED if csr.directed else 0) | (BC_KEEP_ORDER if keep_order else 0)
         self.handle = bc_create_graph(csr.n, csr.row_ptr, csr.col, csr.w, flags)
 
     def info(self) -> dict:

@@ -31,6 +31,9 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
     if (!g->tuned.valid) {
         const int fill = r.batch;
         int64_t sample = std::min<int64_t>(k, std::max<int64_t>(2 * (int64_t)fill, 64));
+        // keep each trial short on large graphs: at most ~4e9 arc-sources
+        while (sample > 64 && (double)sample * (double)std::max<int64_t>(g->nnz, 1) > 4e9)
+            sample /= 2;
         DevBuf scratch;
         scratch.alloc((size_t)g->n * sizeof(double));
         ResolvedOptions c = r;
@@ -57,10 +60,11 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
                     continue;
                 ResolvedOptions t = c;
                 t.wg_threads = nt;
-                t.batch = std::max(1, (int)std::min<int64_t>(
-                                          (int64_t)g->num_cus *
-                                              batched_occupancy(g, nt, t.accumulate == 2),
-                                          sample));
+                int H = 0, per_cu = 1;
+                batched_lds_plan(g, nt, t.accumulate == 2, o.lds_vertices, H, per_cu);
+                t.lds_vertices = H;
+                t.batch = std::max(1, (int)std::min<int64_t>((int64_t)g->num_cus * per_cu,
+                                                             sample));
                 const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
                 if (ms < best) {
                     best = ms;
@@ -91,10 +95,10 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
         r.lane_max = g->tuned.lane_max;
     if (!o.wg_threads && r.wg_threads != g->tuned.wg_threads) {
         r.wg_threads = g->tuned.wg_threads;
+        int H = 0, per_cu = 1;
+        batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, H, per_cu);
+        r.lds_vertices = H;
         if (!o.batch)
-            r.batch = std::max(1, (int)std::min<int64_t>(
-                                      (int64_t)g->num_cus *
-                                          batched_occupancy(g, r.wg_threads, r.accumulate == 2),
-                                      k));
+            r.batch = std::max(1, (int)std::min<int64_t>((int64_t)g->num_cus * per_cu, k));
     }
 }

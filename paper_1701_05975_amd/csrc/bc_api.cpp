@@ -206,8 +206,8 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
         throw bc_error(BC_E_INVAL, "nnz must be below 2^32 - 1");
     if (!row_ptr || (nnz > 0 && (!col || !w)))
         throw bc_error(BC_E_INVAL, "null CSR array");
-    if (flags & ~BC_DIRECTED)
-        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~BC_DIRECTED);
+    if (flags & ~(BC_DIRECTED | BC_KEEP_ORDER))
+        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~(BC_DIRECTED | BC_KEEP_ORDER));
     if (row_ptr[0] != 0 || row_ptr[n] != nnz)
         throw bc_error(BC_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
     int64_t maxdeg = 0;
@@ -268,9 +268,63 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
     hip_check(hipEventCreate(&g->ev_k0), "hipEventCreate");
     hip_check(hipEventCreate(&g->ev_k1), "hipEventCreate");
 
-    upload_arcs(g.get(), n, row_ptr, col, w, g->row, g->arc, g->wt);
-    if (directed) {
-        upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc, g->twt);
+    // Renumber skewed graphs by decreasing in-degree (ties keep the caller's
+    // order): the most frequent arc heads get the lowest ids, whose distances
+    // the batched kernel keeps in LDS.
+    std::vector<int32_t> order;
+    if (!(flags & BC_KEEP_ORDER) && n > 1) {
+        std::vector<int64_t> indeg((size_t)n);
+        for (int32_t v = 0; v < n; ++v)
+            indeg[(size_t)v] = trow[(size_t)v + 1] - trow[(size_t)v];
+        std::vector<int64_t> sorted(indeg);
+        std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
+        const int32_t top = std::max<int32_t>(1, n / 100);
+        int64_t top_arcs = 0;
+        for (int32_t i = 0; i < top; ++i)
+            top_arcs += sorted[(size_t)i];
+        if (nnz > 0 && (double)top_arcs > 0.05 * (double)nnz) {
+            order.resize((size_t)n);
+            for (int32_t v = 0; v < n; ++v)
+                order[(size_t)v] = v;
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                return indeg[(size_t)a] > indeg[(size_t)b];
+            });
+        }
+    }
+    if (!order.empty()) {
+        g->renumbered = true;
+        g->host_iperm.assign((size_t)n, 0);
+        for (int32_t v = 0; v < n; ++v)
+            g->host_iperm[(size_t)order[(size_t)v]] = v;
+        std::vector<int64_t> rrow((size_t)n + 1, 0);
+        std::vector<int32_t> rcol((size_t)nnz), rw((size_t)nnz);
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t o = order[(size_t)v];
+            int64_t at = rrow[(size_t)v];
+            for (int64_t e = row_ptr[o]; e < row_ptr[o + 1]; ++e, ++at) {
+                rcol[(size_t)at] = g->host_iperm[(size_t)col[e]];
+                rw[(size_t)at] = w[e];
+            }
+            rrow[(size_t)v + 1] = at;
+        }
+        upload_arcs(g.get(), n, rrow.data(), rcol.data(), rw.data(), g->row, g->arc, g->wt);
+        if (directed) {
+            build_transpose(n, rrow.data(), rcol.data(), rw.data(), trow, tcol, tw);
+            upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc,
+                        g->twt);
+        }
+        g->perm.alloc((size_t)n * 4);
+        g->iperm.alloc((size_t)n * 4);
+        hip_check(hipMemcpy(g->perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice),
+                  "upload numbering");
+        hip_check(hipMemcpy(g->iperm.p, g->host_iperm.data(), (size_t)n * 4,
+                            hipMemcpyHostToDevice),
+                  "upload numbering");
+    } else {
+        upload_arcs(g.get(), n, row_ptr, col, w, g->row, g->arc, g->wt);
+        if (directed)
+            upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc,
+                        g->twt);
     }
     g->dnode.alloc((size_t)n * sizeof(int32_t));
     g->deg.alloc((size_t)n * sizeof(int32_t));
@@ -396,6 +450,28 @@ int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc)
     return batched_blocks_per_cu(g->packed, nt, atomic_bc);
 }
 
+void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int &H,
+                      int &per_cu)
+{
+    // Workgroups per CU are set by registers; the LDS (160 KB per CU) is then
+    // split among them for the per-source distance caches.
+    const int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc);
+    const size_t lds_cu = 160 * 1024, reserve = 2 * 1024;
+    int cap = (int)((lds_cu / (size_t)std::max(occ, 1) - reserve) / sizeof(uint32_t));
+    if (requested < 0)
+        H = 0;
+    else if (requested > 0)
+        H = std::min(requested, g->n);
+    else
+        H = std::min(cap, g->n);
+    per_cu = H > 0 ? batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, (size_t)H * 4) : occ;
+    if (per_cu < 1) {
+        H = std::min(cap, g->n);
+        per_cu = batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, (size_t)H * 4);
+    }
+    per_cu = std::max(per_cu, 1);
+}
+
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
 {
     ResolvedOptions r;
@@ -405,7 +481,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         o = *opt;
     if (o.mode < 0 || o.mode > BC_MODE_PLAIN)
         throw bc_error(BC_E_INVAL, "unknown mode %d", o.mode);
-    if (o.batch < 0 || o.delta < 0 || o.lane_max_deg < 0 || o.wg_threads < 0)
+    if (o.batch < 0 || o.delta < 0 || o.lane_max_deg < 0 || o.wg_threads < 0 ||
+        o.lds_vertices < -1)
         throw bc_error(BC_E_INVAL, "negative option");
     if (o.accumulate < 0 || o.accumulate > 2)
         throw bc_error(BC_E_INVAL, "unknown accumulate mode %d", o.accumulate);
@@ -417,7 +494,9 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.delta = o.delta ? o.delta : default_delta(g);
     r.lane_max = o.lane_max_deg ? o.lane_max_deg : 32;
     r.accumulate = o.accumulate ? o.accumulate : 1;
-    const int fill = g->num_cus * batched_occupancy(g, r.wg_threads, r.accumulate == 2);
+    int per_cu = 1;
+    batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_vertices, per_cu);
+    const int fill = g->num_cus * per_cu;
     int64_t b = o.batch ? o.batch : fill;
     b = std::min<int64_t>(b, std::max<int64_t>(k, 1));
     // keep the slabs within half of the free device memory
@@ -484,10 +563,13 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->lane_max_deg = r.lane_max;
     st->wg_threads = r.wg_threads;
     st->accumulate = r.accumulate;
+    st->lds_vertices = r.lds_vertices;
 }
 
 static void check_device_errors(const DevCounters &c)
 {
+    if (c.err[0] & BC_ERRBIT_SOURCE)
+        throw bc_error(BC_E_INVAL, "a source in the device source list is out of range");
     if (c.err[0] & BC_ERRBIT_INTERNAL)
         throw bc_error(BC_E_INTERNAL, "an internal iteration bound tripped; result invalid");
     if (c.err[0] & BC_ERRBIT_SIGMA)
@@ -521,6 +603,9 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.bc_out = bc_dev;
         a.item_out = nullptr;
         a.item_err = nullptr;
+        a.iperm = g->iperm_dev();
+        a.perm = g->perm_dev();
+        a.H = r.lds_vertices;
         a.delta = (uint32_t)r.delta;
         a.lane_max = r.lane_max;
         a.stats = &c->stats;
@@ -531,7 +616,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
                   "batched kernel");
         hip_check(hipEventRecord(g->ev_k1, st), "event");
         if (!atomic_bc)
-            hip_check(launch_reduce_partials(a.slab_base, a.L, nslabs, g->n, bc_dev, st),
+            hip_check(launch_reduce_partials(a.slab_base, a.L, nslabs, g->n, bc_dev, a.perm, st),
                       "reduce");
     }
     hip_check(hipEventRecord(e1, st), "event");
@@ -555,6 +640,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
     PlainArgs a;
     a.g = g->view();
+    a.perm = g->perm_dev();
     a.slab_base = (char *)g->plain.base.p;
     a.L = g->plain.L;
     a.ctl = (PlainCtl *)g->plain_ctl.p;
@@ -582,7 +668,8 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
         const bool clear = g->plain_gen_hint > (1 << 30);
         if (clear)
             g->plain_gen_hint = 0;
-        hip_check(launch_plain_source(a, g->packed, grid, src_host[i], (long long)i, clear, st),
+        hip_check(launch_plain_source(a, g->packed, grid, g->internal_id(src_host[i]),
+                                      (long long)i, clear, st),
                   "plain setup");
         // set the iteration bound (host-side value, copied once per source)
         hip_check(launch_fill_u64(&a.ctl->iter_cap, 1, iter_cap, st), "cap");
@@ -676,6 +763,7 @@ bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info)
         i.w_max = g->wmax;
         i.max_out_degree = g->maxdeg;
         i.packed_arcs = g->packed;
+        i.renumbered = g->renumbered;
         i.device_bytes = (int64_t)(g->row.bytes + g->arc.bytes + g->wt.bytes + g->trow.bytes +
                                    g->tarc.bytes + g->twt.bytes);
         *info = i;
@@ -789,7 +877,7 @@ bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t
         ds.alloc((size_t)g->n * 8);
         dl.alloc((size_t)g->n * 8);
         hip_check(launch_export_state((char *)ws.base.p, ws.L, 0, g->n, (int32_t *)dd.p,
-                                      (uint64_t *)ds.p, (double *)dl.p, r.stream),
+                                      (uint64_t *)ds.p, (double *)dl.p, g->perm_dev(), r.stream),
                   "export");
         hip_check(hipStreamSynchronize(r.stream), "synchronize");
         if (d)

@@ -50,6 +50,7 @@ struct ResolvedOptions {
     int wg_threads = 256;
     int accumulate = 1;
     int autotune = 0;
+    int lds_vertices = 0; // H: distances kept in LDS per source
     hipStream_t stream = nullptr;
 };
 
@@ -68,6 +69,7 @@ struct bc_graph {
     int wbytes = 1;
     double avg_deg = 0.0, wmean = 1.0;
     bool packed = false;
+    bool renumbered = false; // device ids are by decreasing in-degree
     uint32_t wshift = 0, wmask = 0;
     int device = 0;
     int num_cus = 1;
@@ -77,6 +79,8 @@ struct bc_graph {
     DevBuf row, arc, wt;    // out-arcs
     DevBuf trow, tarc, twt; // in-arcs (directed graphs only)
     DevBuf dnode, deg;      // per-vertex minimum out-weight and out-degree
+    DevBuf perm, iperm;     // internal -> caller id, caller -> internal id (when renumbered)
+    std::vector<int32_t> host_iperm;
     DevBuf ctl;             // DevCounters
     DevBuf plain_ctl;       // PlainCtl
     DevBuf src_buf;         // uploaded source lists
@@ -91,6 +95,9 @@ struct bc_graph {
     bc_stats last_stats{};
 
     DevGraph view() const;
+    const int32_t *perm_dev() const { return renumbered ? (const int32_t *)perm.p : nullptr; }
+    const int32_t *iperm_dev() const { return renumbered ? (const int32_t *)iperm.p : nullptr; }
+    int32_t internal_id(int32_t v) const { return renumbered ? host_iperm[(size_t)v] : v; }
     ~bc_graph();
 };
 
@@ -103,6 +110,9 @@ struct bc_result {
 SlabLayout slab_layout(int32_t n);
 int default_delta(const bc_graph *g);
 int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc);
+// LDS-resident distances per source and the matching workgroups per CU.
+void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int &H,
+                      int &per_cu);
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
                     const bc_options *opt, double *bc_dev, bc_stats *stats);

@@ -39,7 +39,34 @@ __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slo
     s.fb = (int32_t *)(p + L.fb);
     s.band_off = (int32_t *)(p + L.band_off);
     s.hdr = (int64_t *)(p + L.hdr);
+    s.ld = nullptr;
+    s.H = 0;
     return s;
+}
+
+// Distances: vertices below S.H (the highest in-degree ones after relabelling)
+// live in LDS, the rest in the slab in HBM.  The LDS side goes through an
+// explicit local-address-space pointer so that it compiles to ds_* accesses.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ lds_u32 *lds_ptr(uint32_t *p) { return (lds_u32 *)p; }
+
+__device__ __forceinline__ uint32_t dist_get(const Slab &S, uint32_t u)
+{
+    uint32_t r;
+    if ((int32_t)u < S.H)
+        r = lds_ptr(S.ld)[u];
+    else
+        r = S.d[u];
+    return r;
+}
+
+__device__ __forceinline__ void dist_set(const Slab &S, uint32_t u, uint32_t v)
+{
+    if ((int32_t)u < S.H)
+        lds_ptr(S.ld)[u] = v;
+    else
+        S.d[u] = v;
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,9 @@ struct BatchArgs {
     double *bc_out;               // output (atomic accumulation mode)
     double *const *item_out;      // optional: output of each source-list entry (serving)
     unsigned int *item_err;       // optional: set to 1 for each entry whose counts overflowed
+    const int32_t *iperm;         // caller id -> internal id (null: identity)
+    const int32_t *perm;          // internal id -> caller id (null: identity)
+    int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
     uint32_t delta;               // band width
     int lane_max;
     DevStats *stats;
@@ -40,6 +43,7 @@ struct PlainCtl {
 
 struct PlainArgs {
     DevGraph g;
+    const int32_t *perm;          // internal id -> caller id (null: identity)
     char *slab_base;
     SlabLayout L;
     PlainCtl *ctl;
@@ -52,9 +56,10 @@ struct PlainArgs {
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st);
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, size_t lds_bytes);
 int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc);
 hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
-                                  double *out, hipStream_t st);
+                                  double *out, const int32_t *perm, hipStream_t st);
 hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,
                                long long idx, bool clear_stamps, hipStream_t st);
 hipError_t launch_plain_steps(const PlainArgs &a, bool packed, int grid, int pairs,
@@ -66,6 +71,7 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long lo
 hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, int n,
                              hipStream_t st);
 hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, int n, int32_t *d,
-                               uint64_t *sigma, double *delta, hipStream_t st);
+                               uint64_t *sigma, double *delta, const int32_t *perm,
+                               hipStream_t st);
 hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
                                     hipStream_t st);

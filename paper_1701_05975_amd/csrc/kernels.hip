@@ -60,6 +60,7 @@ __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const
         rc.pend_cnt = &C.pend_cnt;
         rc.err = a.err;
         rc.item_err = a.item_err;
+        rc.perm = ATOMIC_BC ? a.perm : nullptr;
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE>(g, S, rc, st_arcs, st_dag);
         else
@@ -87,11 +88,14 @@ template <bool PACKED, int NT, bool ATOMIC_BC>
 __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 {
     __shared__ WgCtl C;
+    extern __shared__ uint32_t lds_dist[];
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const DevGraph &g = a.g;
     const int n = g.n;
     Slab S = slab_at(a.slab_base, a.L, blockIdx.x);
+    S.ld = lds_dist;
+    S.H = a.H;
     if (!ATOMIC_BC)
         for (int v = tid; v < n; v += NT)
             S.bcp[v] = 0.0;
@@ -111,7 +115,15 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         const long long idx = C.src_idx;
         if (idx >= a.k)
             break;
-        const int32_t s = a.sources[idx];
+        const int32_t s_in = a.sources[idx];
+        if (s_in < 0 || s_in >= n) {
+            // a device-side source list is checked here: report and skip
+            if (tid == 0)
+                atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_SOURCE);
+            __syncthreads();
+            continue;
+        }
+        const int32_t s = a.iperm ? a.iperm[s_in] : s_in;
         double *bc = ATOMIC_BC ? (a.item_out ? a.item_out[idx] : a.bc_out) : S.bcp;
 
         // Queue tags only grow; restart them long before they could wrap.
@@ -123,13 +135,15 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.gen = 0;
         }
         // Initialisation (Alg. 1): d = inf and sigma = 0 everywhere.
-        for (int v = tid; v < n; v += NT) {
+        for (int v = tid; v < S.H; v += NT)
+            S.ld[v] = BC_INF;
+        for (int v = S.H + tid; v < n; v += NT)
             S.d[v] = BC_INF;
+        for (int v = tid; v < n; v += NT)
             S.sigma[v] = 0;
-        }
         __syncthreads();
         if (tid == 0) {
-            S.d[s] = 0;
+            dist_set(S, s, 0);
             S.sigma[s] = 1;
             C.gen += 1;
             S.stamp[s] = C.gen;
@@ -270,6 +284,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 }
             }
         }
+        // The LDS-resident distances go back to the slab so that the slab
+        // holds the complete per-source state.
+        for (int v = tid; v < S.H; v += NT)
+            S.d[v] = S.ld[v];
         __syncthreads();
         if (C.abort) {
             // Leave the slab reusable and report; the result is not valid.
@@ -313,13 +331,14 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 }
 
 // Sum of the per-slab partial centralities, slab after slab.
-__global__ void k_reduce_partials(char *slab_base, SlabLayout L, int nslabs, int n, double *out)
+__global__ void k_reduce_partials(char *slab_base, SlabLayout L, int nslabs, int n, double *out,
+                                  const int32_t *perm)
 {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int b = 0; b < nslabs; ++b)
             acc += ((const double *)(slab_base + (size_t)b * L.stride + L.bcp))[v];
-        out[v] = acc;
+        out[perm ? perm[v] : v] = acc;
     }
 }
 
@@ -502,6 +521,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.pend_cnt = &c->pend_cnt;
         rc.err = a.err;
         rc.item_err = nullptr;
+        rc.perm = a.perm;
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
             sigma_round<PACKED, AG_SCOPE>(g, S, rc, arcs, dag);
@@ -651,15 +671,16 @@ __global__ void k_slab_reset(char *slab_base, SlabLayout L, int nslabs, int n)
 // Copies one slab's per-source state out, with unreached vertices shown as
 // (INT32_MAX, 0, 0).
 __global__ void k_export_state(char *slab_base, SlabLayout L, int slot, int n, int32_t *d,
-                               uint64_t *sigma, double *delta)
+                               uint64_t *sigma, double *delta, const int32_t *perm)
 {
     Slab S = slab_at(slab_base, L, slot);
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const uint32_t dv = S.d[v];
         const bool r = dv != BC_INF;
-        d[v] = (int32_t)dv;
-        sigma[v] = r ? S.sigma[v] : 0ull;
-        delta[v] = r ? S.delta[v] : 0.0;
+        const int32_t o = perm ? perm[v] : v;
+        d[o] = (int32_t)dv;
+        sigma[o] = r ? S.sigma[v] : 0ull;
+        delta[o] = r ? S.delta[v] : 0.0;
     }
 }
 
@@ -687,7 +708,11 @@ __global__ void k_graph_vertex_info(DevGraph g, int32_t *dnode, int32_t *deg)
 template <bool PACKED, int NT, bool ATOMIC>
 static void launch_batched_t(const BatchArgs &a, int nslabs, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC>), dim3(nslabs), dim3(NT), 0, st, a);
+    const size_t lds = (size_t)a.H * sizeof(uint32_t);
+    if (lds > 48 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC>), dim3(nslabs), dim3(NT), lds, st, a);
 }
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
@@ -716,11 +741,22 @@ hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_b
 
 int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc)
 {
+    return batched_blocks_per_cu_lds(packed, nt, atomic_bc, 0);
+}
+
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, size_t lds_bytes)
+{
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
 #define BC_OCC(P, T, A)                                                                         \
-    if (packed == P && nt == T && atomic_bc == A)                                               \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A>, T, 0);
+    if (packed == P && nt == T && atomic_bc == A) {                                             \
+        if (lds_bytes > 48 * 1024)                                                              \
+            (void)hipFuncSetAttribute((const void *)k_batched<P, T, A>,                         \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,               \
+                                      (int)lds_bytes);                                          \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A>, T,        \
+                                                         lds_bytes);                            \
+    }
     BC_OCC(true, 256, false)
     BC_OCC(true, 256, true)
     BC_OCC(true, 512, false)
@@ -742,7 +778,7 @@ int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc)
 }
 
 hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
-                                  double *out, hipStream_t st)
+                                  double *out, const int32_t *perm, hipStream_t st)
 {
     int blocks = (n + 255) / 256;
     if (blocks > 4096)
@@ -750,7 +786,7 @@ hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nsla
     if (blocks < 1)
         blocks = 1;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, st, slab_base, L, nslabs, n,
-                       out);
+                       out, perm);
     return hipGetLastError();
 }
 
@@ -831,7 +867,8 @@ hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, i
 }
 
 hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, int n, int32_t *d,
-                               uint64_t *sigma, double *delta, hipStream_t st)
+                               uint64_t *sigma, double *delta, const int32_t *perm,
+                               hipStream_t st)
 {
     int blocks = (n + 255) / 256;
     if (blocks > 4096)
@@ -839,7 +876,7 @@ hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, i
     if (blocks < 1)
         blocks = 1;
     hipLaunchKernelGGL(k_export_state, dim3(blocks), dim3(256), 0, st, slab_base, L, slot, n, d,
-                       sigma, delta);
+                       sigma, delta, perm);
     return hipGetLastError();
 }
 

@@ -19,6 +19,15 @@ __device__ __forceinline__ uint32_t atomic_min_u32(uint32_t *p, uint32_t v)
 }
 
 template <int SCOPE>
+__device__ __forceinline__ uint32_t dist_min(const Slab &S, uint32_t u, uint32_t v)
+{
+    if ((int32_t)u < S.H)
+        return __hip_atomic_fetch_min(lds_ptr(S.ld) + u, v, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    return atomic_min_u32<SCOPE>(&S.d[u], v);
+}
+
+template <int SCOPE>
 __device__ __forceinline__ int atomic_xchg_i32(int32_t *p, int32_t v)
 {
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, SCOPE);
@@ -79,8 +88,8 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
                                       uint32_t &far_min, uint64_t &nimp)
 {
     bool imp = false;
-    if (nd < S.d[u]) {
-        uint32_t old = atomic_min_u32<SCOPE>(&S.d[u], nd);
+    if (nd < dist_get(S, u)) {
+        uint32_t old = dist_min<SCOPE>(S, u, nd);
         imp = nd < old;
     }
     bool pn = false, pm = false, pf = false;
@@ -121,7 +130,7 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
             const int v = c.items[i];
             beg = g.row[v];
             end = g.row[v + 1];
-            dv = S.d[v];
+            dv = dist_get(S, v);
         }
         const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
         if (valid && !heavy) {
@@ -177,7 +186,7 @@ __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uin
         uint32_t dv = 0;
         if (valid) {
             v = c.far_in[i];
-            dv = S.d[v];
+            dv = dist_get(S, v);
         }
         const bool drop = valid && dv < c.thr_old;
         const bool move = valid && !drop && dv < c.thr;
@@ -218,6 +227,8 @@ struct RoundCtx {
     int *pend_cnt;
     unsigned long long *err; // [0] error bits, [1] first overflowing source index
     unsigned int *item_err;  // optional per-source-entry overflow flags
+    const int32_t *perm;     // optional: caller's vertex id of each internal vertex, used
+                             // when adding into a caller-indexed output
 };
 
 __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
@@ -255,14 +266,14 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
         const bool heavy = valid && !is_src && (end - beg) > (uint32_t)c.lane_max;
         bool pend = false;
         if (valid && !is_src && !heavy) {
-            const uint32_t dv = S.d[v];
+            const uint32_t dv = dist_get(S, v);
             uint64_t acc = 0;
             bool ready = true, ovf = false;
             uint32_t tight = 0;
             for (uint32_t e = beg; e < end; ++e) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
-                if (S.d[u] + w == dv) {
+                if (dist_get(S, u) + w == dv) {
                     const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
                     if (su == 0) {
                         ready = false;
@@ -297,14 +308,14 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             const int32_t hv = __shfl(v, l);
             const uint32_t hb = (uint32_t)__shfl((int)beg, l);
             const uint32_t he = (uint32_t)__shfl((int)end, l);
-            const uint32_t dv = S.d[hv];
+            const uint32_t dv = dist_get(S, hv);
             uint64_t acc = 0;
             bool ready = true, ovf = false;
             uint32_t tight = 0;
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
-                if (S.d[u] + w == dv) {
+                if (dist_get(S, u) + w == dv) {
                     const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
                     if (su == 0) {
                         ready = false;
@@ -360,14 +371,14 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
         const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
         bool pend = false;
         if (valid && !heavy) {
-            const uint32_t dv = S.d[v];
+            const uint32_t dv = dist_get(S, v);
             const double sv = (double)S.sigma[v];
             double acc = 0.0;
             bool ready = true;
             for (uint32_t e = beg; e < end; ++e) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                const uint32_t du = S.d[u];
+                const uint32_t du = dist_get(S, u);
                 if (du != BC_INF && du == dv + w) {
                     const double dl = load_f64<SCOPE>(&S.delta[u]);
                     if (dl < 0.0) {
@@ -380,10 +391,11 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             if (ready) {
                 store_f64<SCOPE>(&S.delta[v], acc);
                 if (v != c.s) {
+                    const int32_t o = c.perm ? c.perm[v] : v;
                     if (ATOMIC_BC)
-                        unsafeAtomicAdd(&bc[v], acc);
+                        unsafeAtomicAdd(&bc[o], acc);
                     else
-                        bc[v] += acc;
+                        bc[o] += acc;
                 }
             }
             pend = !ready;
@@ -400,14 +412,14 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             const int32_t hv = __shfl(v, l);
             const uint32_t hb = (uint32_t)__shfl((int)beg, l);
             const uint32_t he = (uint32_t)__shfl((int)end, l);
-            const uint32_t dv = S.d[hv];
+            const uint32_t dv = dist_get(S, hv);
             const double sv = (double)S.sigma[hv];
             double acc = 0.0;
             bool ready = true;
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                const uint32_t du = S.d[u];
+                const uint32_t du = dist_get(S, u);
                 if (du != BC_INF && du == dv + w) {
                     const double dl = load_f64<SCOPE>(&S.delta[u]);
                     if (dl < 0.0) {
@@ -422,10 +434,11 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             if (all_ready && lane == 0) {
                 store_f64<SCOPE>(&S.delta[hv], acc);
                 if (hv != c.s) {
+                    const int32_t o = c.perm ? c.perm[hv] : hv;
                     if (ATOMIC_BC)
-                        unsafeAtomicAdd(&bc[hv], acc);
+                        unsafeAtomicAdd(&bc[o], acc);
                     else
-                        bc[hv] += acc;
+                        bc[o] += acc;
                 }
             }
             const bool p = !all_ready && lane == 0;

@@ -48,6 +48,7 @@ struct SweepCtx {
     bool busy = false;
     int cap = 0;
     int slots = 0;
+    int lds_vertices = 0;
     std::vector<bcserve::SweepItem> items;
     ~SweepCtx()
     {
@@ -171,6 +172,9 @@ class HipExec {
         a.bc_out = nullptr;
         a.item_out = (double *const *)c->d_out.p;
         a.item_err = (unsigned int *)c->d_err.p;
+        a.iperm = g->iperm_dev();
+        a.perm = g->perm_dev();
+        a.H = c->lds_vertices;
         a.delta = (uint32_t)delta_for(g);
         a.lane_max = lane_max_for(g);
         a.stats = &dc->stats;
@@ -271,7 +275,9 @@ class HipExec {
     {
         bc_graph *g = e.g;
         const int nt = wg_for(g);
-        const int fill = g->num_cus * batched_occupancy(g, nt, true);
+        int H = 0, per_cu = 1;
+        batched_lds_plan(g, nt, true, opts_.compute.lds_vertices, H, per_cu);
+        const int fill = g->num_cus * per_cu;
         const SlabLayout L = slab_layout(g->n);
         int slots = opts_.slots_per_sweep ? opts_.slots_per_sweep : fill;
         const int64_t by_mem = (int64_t)(opts_.slab_bytes_per_sweep / std::max<size_t>(L.stride, 1));
@@ -283,6 +289,7 @@ class HipExec {
             c->gidx = gidx;
             c->slots = slots;
             c->cap = cap;
+            c->lds_vertices = H;
             hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
             hip_check(hipEventCreateWithFlags(&c->done, hipEventDisableTiming), "event");
             c->ws.L = L;
@@ -411,7 +418,7 @@ bc_status bc_server_create(const bc_server_opts *o, bc_server **out)
         if (sv->opts.result_budget_bytes <= 0)
             sv->opts.result_budget_bytes = (int64_t)(free_b / 4);
         if (sv->opts.slab_bytes_per_sweep <= 0)
-            sv->opts.slab_bytes_per_sweep = (int64_t)1 << 32;
+            sv->opts.slab_bytes_per_sweep = (int64_t)(free_b / 16);
         if (sv->opts.max_active <= 0)
             sv->opts.max_active = 64;
         sv->exec.reset(new HipExec(sv->opts, (size_t)256 << 20));

@@ -43,6 +43,8 @@ struct Slab {
     int32_t *fa, *fb;  // far piles
     int32_t *band_off; // band b = order[band_off[b] .. band_off[b+1])
     int64_t *hdr;      // [0] = last queue tag used by this slab
+    uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
+    int32_t H;         // number of LDS-resident distances (0 = none)
 };
 
 // Byte offsets of the slab arrays inside one slot (all 256-byte aligned).
@@ -56,6 +58,7 @@ struct SlabLayout {
 // ---------------------------------------------------------------------------
 #define BC_ERRBIT_SIGMA 1
 #define BC_ERRBIT_INTERNAL 2
+#define BC_ERRBIT_SOURCE 4
 
 struct DevStats {
     unsigned long long reached, arcs, dag, improvements, bands, iterations, sigma_rounds,

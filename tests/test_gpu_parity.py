@@ -31,6 +31,8 @@ OPTION_SETS = [
     dict(wg_threads=512, batch=3),
     dict(accumulate=2),
     dict(mode=bc.BC_MODE_PLAIN, delta=1, lane_max_deg=1),
+    dict(lds_vertices=-1),
+    dict(lds_vertices=5, wg_threads=256),
 ]
 
 
@@ -70,6 +72,9 @@ def small_graphs():
         (200, 0.03, 1, 2, 6, True), (513, 0.012, 1, 9, 7, False), (1037, 0.006, 1, 1000, 8, True),
     ]:
         out.append(gg.random_graph(n, p, wl, wh, seed=seed, directed=directed))
+    # skewed graphs: renumbered by in-degree on the device
+    out.append(gg.ba_graph(700, 3, 1, 20, seed=9))
+    out.append(gg.rmat_graph(10, 8 << 10, .57, .19, .19, 1, 9, seed=10))
     return out
 
 
@@ -85,6 +90,38 @@ def test_small_graphs_all_sources_every_option_set(g):
         for s in srcs:
             check_state(g, G, s, **opts)
     G.close()
+
+
+def test_renumbered_graph_matches_caller_order():
+    g = gg.ba_graph(3000, 4, 1, 300, seed=12)
+    A = bc.Graph(g)
+    B = bc.Graph(g, keep_order=True)
+    assert A.info()["renumbered"] == 1 and B.info()["renumbered"] == 0
+    srcs = np.arange(0, 3000, 5, dtype=np.int32)
+    a, _ = A.bc(srcs)
+    b, _ = B.bc(srcs)
+    rel_close(a, b, 1e-12)
+    for s in (0, 7, 2999):
+        da, sa, la = A.source_state(s)
+        db, sb, lb = B.source_state(s)
+        assert np.array_equal(da, db) and np.array_equal(sa, sb)
+        rel_close(la, lb, 1e-12)
+    rel_close(a, oracle.oracle_bc(g, srcs), 1e-9)
+
+
+def test_device_sources_out_of_range_rejected():
+    torch = pytest.importorskip("torch")
+    g = gg.path_graph(40)
+    G = bc.Graph(g)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    for bad in (-1, 40):
+        s_dev = torch.tensor([3, bad, 5], dtype=torch.int32, device="cuda")
+        with pytest.raises(bc.BCError) as ei:
+            bc.bc_compute_device(G.handle, s_dev.data_ptr(), 3, out.data_ptr())
+        assert ei.value.status == bc.BC_E_INVAL
+    # still usable afterwards
+    got, _ = G.bc(np.array([3, 5], np.int32))
+    rel_close(got, oracle.oracle_bc(g, [3, 5]), 1e-12)
 
 
 def test_schedules_give_bit_identical_distances_and_counts():
