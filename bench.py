@@ -56,6 +56,9 @@ def serving_graphs():
 def run_serving(args):
     """Open-loop serving run: Poisson arrivals at a fixed rate, latency from
     arrival to completion measured inside the server."""
+    # sweeps of different graphs run on their own streams; give them hardware
+    # queues of their own (HIP reads this before the runtime starts)
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
     import torch  # noqa: F401  (one HIP runtime for the process)
     from paper_1701_05975_amd import bc, graphgen as gg
 
@@ -145,10 +148,10 @@ HBM_PEAK_GBS = 8000.0
 # (python bench.py --autotune prints them); pinned so that the timed and the
 # profiled command launch identical kernels.
 TUNED = {
-    "ba100k": dict(delta=50, wg_threads=512, lane_max_deg=16),
-    "er1000": dict(),
-    "grid1000": dict(),
-    "rmat22": dict(),
+    "ba100k": dict(delta=50, wg_threads=1024, lane_max_deg=32),
+    "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
+    "grid1000": dict(delta=130, wg_threads=512, lane_max_deg=8),
+    "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
 }
 
 
@@ -343,6 +346,10 @@ def main():
             "reached": last.reached, "arcs_out_reached": last.arcs_out_reached,
             "dag_arcs": last.dag_arcs, "improvements": last.improvements,
             "bands": last.bands, "iterations": last.iterations,
+            "sigma_rounds": last.sigma_rounds, "delta_rounds": last.delta_rounds,
+            "phase_share": {k: round(v / max(1, sum(last.phase_ticks)), 4) for k, v in
+                            zip(["init", "expand", "counts", "dependencies", "split"],
+                                list(last.phase_ticks))},
         },
         "roofline": roofline,
         "plain": plain,

@@ -142,6 +142,9 @@ typedef struct {
     double algo_bytes;        /* algorithmic bytes of the work (see bc_algo_bytes) */
     double kernel_ms;         /* device time of the main kernel launches alone (HIP events) */
     int64_t kernel_launches;  /* number of main kernel launches timed in kernel_ms */
+    int64_t phase_ticks[5];   /* batched form: device clock ticks summed over workgroups spent
+                                 in initialisation, frontier expansion, count rounds,
+                                 dependency rounds and far-pile splits */
     int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices;
 } bc_stats;
 
@@ -226,8 +229,8 @@ typedef struct {
                                      free memory at creation */
     int32_t max_active;           /* admitted, unfinished requests; 0 = 64 */
     int32_t sweeps_per_graph;     /* concurrent sweeps per graph; 0 = 2 */
-    int32_t slots_per_sweep;      /* sources in flight per sweep; 0 = fill the GPU within the
-                                     slab memory */
+    int32_t slots_per_sweep;      /* sources in flight per sweep; 0 = a quarter of the GPU's
+                                     resident workgroups, within the slab memory */
     int32_t items_per_sweep;      /* sources per sweep; 0 = twice the slots */
     bc_options compute;           /* delta, lane_max_deg and wg_threads of the sweeps; 0 fields
                                      take the graph's autotuned (else default) values; mode,

@@ -62,12 +62,15 @@ class bc_stats(ctypes.Structure):
                 ("sigma_rounds", ctypes.c_int64), ("delta_rounds", ctypes.c_int64),
                 ("first_bad_source", ctypes.c_int64), ("algo_bytes", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("phase_ticks", ctypes.c_int64 * 5),
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["phase_ticks"] = list(self.phase_ticks)
+        return d
 
 
 class bc_graph_info(ctypes.Structure):

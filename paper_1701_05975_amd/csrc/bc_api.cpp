@@ -366,6 +366,8 @@ bc_graph::~bc_graph()
         (void)hipStreamSynchronize(stream);
         (void)hipStreamDestroy(stream);
     }
+    if (plain_exec)
+        (void)hipGraphExecDestroy(plain_exec);
     if (ev_k0)
         (void)hipEventDestroy(ev_k0);
     if (ev_k1)
@@ -381,7 +383,7 @@ bc_graph::~bc_graph()
 // ---------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-SlabLayout slab_layout(int32_t n)
+SlabLayout slab_layout(int32_t n, int64_t pred_slots)
 {
     SlabLayout L;
     const size_t nn = (size_t)n;
@@ -404,6 +406,9 @@ SlabLayout slab_layout(int32_t n)
     L.fb = take(4 * nn);
     L.band_off = take(4 * (nn + 2));
     L.hdr = take(64);
+    L.scnt = take(4 * nn);
+    L.pcnt = take(4 * nn);
+    L.preds = take(4 * (size_t)std::max<int64_t>(pred_slots, 1));
     L.stride = o;
     return L;
 }
@@ -413,7 +418,8 @@ static void ensure_slabs(bc_graph *g, Workspace &ws, int nslabs, hipStream_t st)
     if (ws.base.p && ws.nslabs >= nslabs)
         return;
     ws.base.release();
-    ws.L = slab_layout(g->n);
+    // only the batched form records the shortest-path DAG (one slot per in-arc)
+    ws.L = slab_layout(g->n, &ws == &g->batched ? g->nnz : 0);
     const size_t bytes = ws.L.stride * (size_t)nslabs;
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
@@ -502,7 +508,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     // keep the slabs within half of the free device memory
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-    const size_t stride = slab_layout(g->n).stride;
+    const size_t stride = slab_layout(g->n, g->nnz).stride;
     const size_t have = g->batched.base.p ? (size_t)g->batched.nslabs * stride : 0;
     const int64_t by_mem = (int64_t)((free_b + have) / 2 / std::max<size_t>(stride, 1));
     if (by_mem < 1)
@@ -552,6 +558,8 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->iterations = (int64_t)c.stats.iterations;
     st->sigma_rounds = (int64_t)c.stats.sigma_rounds;
     st->delta_rounds = (int64_t)c.stats.delta_rounds;
+    for (int i = 0; i < 5; ++i)
+        st->phase_ticks[i] = (int64_t)c.stats.ticks[i];
     st->first_bad_source = (c.err[0] & BC_ERRBIT_SIGMA) ? (int64_t)c.err[1] : -1;
     // Per-source byte model summed over sources: the n-dependent term once per source.
     st->algo_bytes = (double)k * 20.0 * (double)g->n +
@@ -644,7 +652,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     a.slab_base = (char *)g->plain.base.p;
     a.L = g->plain.L;
     a.ctl = (PlainCtl *)g->plain_ctl.p;
-    a.bc_out = bc_dev;
+    a.bc_out = nullptr; // the output travels in the control block
     a.delta = (uint32_t)r.delta;
     a.lane_max = r.lane_max;
     DevCounters *c = (DevCounters *)g->ctl.p;
@@ -659,6 +667,31 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
         hip_check(hipStreamSynchronize(st), "ctl");
         g->plain_ctl_ready = true;
     }
+    // The sweep loop of the plain form is a captured graph of (step, control)
+    // pairs, replayed until the phase machine reports completion.  Its kernel
+    // arguments only name per-graph buffers, so one capture serves every call
+    // with the same band width and lane threshold.
+    const int PLAIN_GRAPH_PAIRS = 32;
+    if (!g->plain_exec || g->plain_exec_delta != a.delta || g->plain_exec_lane_max != a.lane_max ||
+        g->plain_exec_slab != (const void *)a.slab_base) {
+        if (g->plain_exec) {
+            (void)hipGraphExecDestroy(g->plain_exec);
+            g->plain_exec = nullptr;
+        }
+        hip_check(hipStreamSynchronize(g->stream), "synchronize");
+        hip_check(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "capture");
+        hipError_t le = launch_plain_steps(a, g->packed, grid, PLAIN_GRAPH_PAIRS, g->stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(g->stream, &graph);
+        hip_check(le, "capture launches");
+        hip_check(ce, "end capture");
+        hipError_t ie = hipGraphInstantiate(&g->plain_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(ie, "instantiate");
+        g->plain_exec_delta = a.delta;
+        g->plain_exec_lane_max = a.lane_max;
+        g->plain_exec_slab = (const void *)a.slab_base;
+    }
     const unsigned long long iter_cap = 8ull * (unsigned long long)g->n + 1024ull;
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
@@ -669,15 +702,14 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
         if (clear)
             g->plain_gen_hint = 0;
         hip_check(launch_plain_source(a, g->packed, grid, g->internal_id(src_host[i]),
-                                      (long long)i, clear, st),
+                                      (long long)i, clear, bc_dev, st),
                   "plain setup");
         // set the iteration bound (host-side value, copied once per source)
         hip_check(launch_fill_u64(&a.ctl->iter_cap, 1, iter_cap, st), "cap");
-        int pairs = 8;
         long long total_pairs = 0;
         for (;;) {
-            hip_check(launch_plain_steps(a, g->packed, grid, pairs, st), "plain steps");
-            total_pairs += pairs;
+            hip_check(hipGraphLaunch(g->plain_exec, st), "plain sweep");
+            total_pairs += PLAIN_GRAPH_PAIRS;
             hip_check(hipMemcpyAsync(g->host_plain, a.ctl, sizeof(PlainCtl),
                                      hipMemcpyDeviceToHost, st),
                       "read phase");
@@ -686,7 +718,6 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
                 break;
             if (total_pairs > 64ll * (long long)iter_cap + 4096)
                 throw bc_error(BC_E_INTERNAL, "plain phase machine did not finish");
-            pairs = std::min(pairs * 2, 256);
         }
         g->plain_gen_hint = g->host_plain->gen;
         if (g->host_plain->abort)

@@ -88,6 +88,11 @@ struct bc_graph {
     PlainCtl *host_plain = nullptr;
     bool plain_ctl_ready = false;
     long long plain_gen_hint = 0;
+    // captured sweep of the plain form: PLAIN_GRAPH_PAIRS (step, control) pairs
+    hipGraphExec_t plain_exec = nullptr;
+    uint32_t plain_exec_delta = 0;
+    int plain_exec_lane_max = 0;
+    const void *plain_exec_slab = nullptr;
 
     Workspace batched, plain;
     TunedOptions tuned;
@@ -107,7 +112,7 @@ struct bc_result {
     bc_stats stats{};
 };
 
-SlabLayout slab_layout(int32_t n);
+SlabLayout slab_layout(int32_t n, int64_t pred_slots);
 int default_delta(const bc_graph *g);
 int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc);
 // LDS-resident distances per source and the matching workgroups per CU.

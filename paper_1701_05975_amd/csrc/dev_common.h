@@ -41,6 +41,9 @@ __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slo
     s.hdr = (int64_t *)(p + L.hdr);
     s.ld = nullptr;
     s.H = 0;
+    s.scnt = (int32_t *)(p + L.scnt);
+    s.pcnt = (int32_t *)(p + L.pcnt);
+    s.preds = (int32_t *)(p + L.preds);
     return s;
 }
 

@@ -39,6 +39,7 @@ struct PlainCtl {
     unsigned long long iters, iter_cap;
     int abort, finished;
     unsigned long long srounds, drounds;
+    double *bc_out; // caller-indexed output of the current computation
 };
 
 struct PlainArgs {
@@ -61,7 +62,7 @@ int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc);
 hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
                                   double *out, const int32_t *perm, hipStream_t st);
 hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,
-                               long long idx, bool clear_stamps, hipStream_t st);
+                               long long idx, bool clear_stamps, double *bc_out, hipStream_t st);
 hipError_t launch_plain_steps(const PlainArgs &a, bool packed, int grid, int pairs,
                               hipStream_t st);
 hipError_t launch_plain_clear_infar(const PlainArgs &a, hipStream_t st);

@@ -29,7 +29,20 @@ struct WgCtl {
     long long src_idx;
     unsigned long long iters;
     unsigned int bands, srounds, drounds;
+    unsigned long long ticks[5]; // per-phase device time of this workgroup
 };
+
+// Phase timing of one workgroup: thread 0 reads the constant-rate device
+// clock at phase boundaries (phases: 0 init, 1 expansion, 2 counts,
+// 3 dependencies, 4 far split).
+__device__ __forceinline__ void phase_mark(WgCtl &C, long long &t0, int phase)
+{
+    if (threadIdx.x == 0) {
+        const long long t = wall_clock64();
+        C.ticks[phase] += (unsigned long long)(t - t0);
+        t0 = t;
+    }
+}
 
 // Runs the count (or dependency) rounds over the members order[b0, b1) of
 // one band inside a workgroup.  Returns false if the round bound tripped.
@@ -62,7 +75,7 @@ __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const
         rc.item_err = a.item_err;
         rc.perm = ATOMIC_BC ? a.perm : nullptr;
         if (SIGMA)
-            sigma_round<PACKED, WG_SCOPE>(g, S, rc, st_arcs, st_dag);
+            sigma_round<PACKED, WG_SCOPE, true>(g, S, rc, st_arcs, st_dag);
         else
             delta_round<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, rc, bc);
         __syncthreads();
@@ -104,7 +117,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         C.gen = (int32_t)S.hdr[0];
         C.iters = 0;
         C.bands = C.srounds = C.drounds = 0;
+        for (int i = 0; i < 5; ++i)
+            C.ticks[i] = 0;
     }
+    long long tmark = tid == 0 ? wall_clock64() : 0;
     __syncthreads();
     const unsigned long long iter_cap = 8ull * (unsigned long long)n + 1024ull;
 
@@ -139,8 +155,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             S.ld[v] = BC_INF;
         for (int v = S.H + tid; v < n; v += NT)
             S.d[v] = BC_INF;
-        for (int v = tid; v < n; v += NT)
+        for (int v = tid; v < n; v += NT) {
             S.sigma[v] = 0;
+            S.scnt[v] = 0;
+        }
         __syncthreads();
         if (tid == 0) {
             dist_set(S, s, 0);
@@ -165,6 +183,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             C.iters = 0;
         }
         __syncthreads();
+        phase_mark(C, tmark, 0);
 
         // Forward pass: near-far bands of width delta.
         for (;;) {
@@ -202,6 +221,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 }
                 __syncthreads();
             }
+            phase_mark(C, tmark, 1);
             if (C.abort)
                 break;
             // The band is closed: its members order[b0, b1) have final distances.
@@ -215,6 +235,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                     break;
                 }
             }
+            phase_mark(C, tmark, 2);
             if (tid == 0) {
                 if (b1 > b0) {
                     C.nbands += 1;
@@ -269,21 +290,52 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.far_cnt = C.kept_cnt;
             }
             __syncthreads();
+            phase_mark(C, tmark, 4);
         }
 
-        // Backward pass: bands in reverse order (Alg. 3).
+        // Backward pass (Alg. 3): Kahn's order over the recorded shortest-path
+        // DAG, from the vertices without successors towards the source.
         if (!C.abort) {
-            const int nb = C.nbands;
-            for (int b = nb - 1; b >= 0; --b) {
-                const int b0 = S.band_off[b], b1 = S.band_off[b + 1];
-                if (!wg_band_rounds<PACKED, NT, false, ATOMIC_BC>(g, S, C, a, s, idx, b0, b1, bc,
-                                                                   st_arcs, st_dag)) {
+            if (tid == 0)
+                C.pend_cnt = 0;
+            __syncthreads();
+            kahn_leaves(S, S.order, C.order_cnt, tid / WAVE, NT / WAVE, S.qa, &C.pend_cnt);
+            __syncthreads();
+            int len = C.pend_cnt;
+            __syncthreads();
+            const int32_t *items = S.qa;
+            int which = 0;
+            const int cap = C.order_cnt + 2;
+            for (int step = 0; len > 0; ++step) {
+                if (step > cap) {
                     if (tid == 0)
                         C.abort = 1;
                     break;
                 }
+                if (tid == 0)
+                    C.pend_cnt = 0;
+                __syncthreads();
+                KahnCtx kc;
+                kc.items = items;
+                kc.len = len;
+                kc.worker = tid / WAVE;
+                kc.nworkers = NT / WAVE;
+                kc.lane_max = a.lane_max;
+                kc.s = s;
+                kc.next_q = which ? S.qa : S.qb;
+                kc.next_cnt = &C.pend_cnt;
+                kc.perm = ATOMIC_BC ? a.perm : nullptr;
+                kahn_step<WG_SCOPE, ATOMIC_BC>(g, S, kc, bc);
+                __syncthreads();
+                len = C.pend_cnt;
+                __syncthreads();
+                items = which ? S.qa : S.qb;
+                which ^= 1;
+                if (tid == 0)
+                    C.drounds++;
             }
         }
+        phase_mark(C, tmark, 3);
         // The LDS-resident distances go back to the slab so that the slab
         // holds the complete per-source state.
         for (int v = tid; v < S.H; v += NT)
@@ -327,6 +379,8 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         S.hdr[0] = C.gen;
         atomicAdd(&a.stats->sigma_rounds, (unsigned long long)C.srounds);
         atomicAdd(&a.stats->delta_rounds, (unsigned long long)C.drounds);
+        for (int i = 0; i < 5; ++i)
+            atomicAdd(&a.stats->ticks[i], C.ticks[i]);
     }
 }
 
@@ -396,7 +450,7 @@ __global__ void k_plain_init(PlainArgs a)
     }
 }
 
-__global__ void k_plain_setup(PlainArgs a, int32_t s, long long idx)
+__global__ void k_plain_setup(PlainArgs a, int32_t s, long long idx, double *bc_out)
 {
     Slab S = slab_at(a.slab_base, a.L, 0);
     PlainCtl *c = a.ctl;
@@ -409,6 +463,7 @@ __global__ void k_plain_setup(PlainArgs a, int32_t s, long long idx)
     S.band_off[0] = 0;
     c->s = s;
     c->src_idx = idx;
+    c->bc_out = bc_out;
     c->cur = 0;
     c->fcur = 0;
     c->pcur = 0;
@@ -524,7 +579,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.perm = a.perm;
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
-            sigma_round<PACKED, AG_SCOPE>(g, S, rc, arcs, dag);
+            sigma_round<PACKED, AG_SCOPE, false>(g, S, rc, arcs, dag);
             unsigned long long x = arcs, y = dag;
             for (int o = 32; o > 0; o >>= 1) {
                 x += __shfl_xor(x, o);
@@ -537,7 +592,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
                     atomicAdd(&a.stats->dag, y);
             }
         } else {
-            delta_round<PACKED, AG_SCOPE, false>(g, S, rc, a.bc_out);
+            delta_round<PACKED, AG_SCOPE, false>(g, S, rc, c->bc_out);
         }
     }
 }
@@ -791,7 +846,7 @@ hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nsla
 }
 
 hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,
-                               long long idx, bool clear_stamps, hipStream_t st)
+                               long long idx, bool clear_stamps, double *bc_out, hipStream_t st)
 {
     int fb = (a.g.n + 255) / 256;
     if (fb > 2048)
@@ -801,7 +856,7 @@ hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_
     if (clear_stamps)
         hipLaunchKernelGGL(k_plain_clear_stamps, dim3(fb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_plain_init, dim3(fb), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_plain_setup, dim3(1), dim3(1), 0, st, a, s, idx);
+    hipLaunchKernelGGL(k_plain_setup, dim3(1), dim3(1), 0, st, a, s, idx, bc_out);
     (void)packed;
     (void)grid;
     return hipGetLastError();

@@ -83,12 +83,17 @@ struct ExpandCtx {
     int *far_cnt;
 };
 
+// Arcs handled per step by a lane that walks its own row: their heads and
+// the heads' distances are loaded together, so several independent loads per
+// lane are in flight instead of one dependent chain per arc.
+#define LANE_UNROLL 4
+
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
-                                      uint32_t &far_min, uint64_t &nimp)
+                                      uint32_t du, uint32_t &far_min, uint64_t &nimp)
 {
     bool imp = false;
-    if (nd < dist_get(S, u)) {
+    if (nd < du) {
         uint32_t old = dist_min<SCOPE>(S, u, nd);
         imp = nd < old;
     }
@@ -134,10 +139,22 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
         }
         const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
         if (valid && !heavy) {
-            for (uint32_t e = beg; e < end; ++e) {
-                uint32_t u, w;
-                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE>(S, c, u, dv + w, far_min, nimp);
+            for (uint32_t e0 = beg; e0 < end; e0 += LANE_UNROLL) {
+                uint32_t u[LANE_UNROLL], w[LANE_UNROLL], du[LANE_UNROLL];
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j) {
+                    u[j] = 0;
+                    w[j] = 0;
+                    if (e0 + j < end)
+                        arc_at<PACKED>(g.arc, g.wt, e0 + j, g.wshift, g.wmask, u[j], w[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j)
+                    du[j] = e0 + j < end ? dist_get(S, u[j]) : 0u;
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j)
+                    if (e0 + j < end)
+                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], far_min, nimp);
             }
         }
         uint64_t hm = __ballot(heavy);
@@ -150,7 +167,7 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE>(S, c, u, hd + w, far_min, nimp);
+                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), far_min, nimp);
             }
         }
     }
@@ -243,7 +260,12 @@ __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 // is the sum of sigma[u] over arcs (u, v, w) with d[u] + w == d[v].  With
 // weights >= 1 every such u has d[u] < d[v], so it belongs to this band or
 // an earlier one.
-template <bool PACKED, int SCOPE>
+//
+// With RECORD, the tight in-arcs of v are also written to preds[trow[v] ..]
+// (the slice of v's own in-row, so no allocation is needed), pcnt[v] holds
+// their number and every recorded predecessor's successor count scnt is
+// incremented once v is final; the dependency pass then walks this DAG.
+template <bool PACKED, int SCOPE, bool RECORD>
 __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
 {
@@ -261,8 +283,12 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                 arcs += g.row[v + 1] - g.row[v];
         }
         const bool is_src = valid && v == c.s;
-        if (is_src)
-            store_f64<SCOPE>(&S.delta[v], -1.0); // sigma[s] = 1 was set at initialisation
+        if (is_src) {
+            // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
+            store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
+            if (RECORD)
+                S.pcnt[v] = 0;
+        }
         const bool heavy = valid && !is_src && (end - beg) > (uint32_t)c.lane_max;
         bool pend = false;
         if (valid && !is_src && !heavy) {
@@ -270,19 +296,33 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             uint64_t acc = 0;
             bool ready = true, ovf = false;
             uint32_t tight = 0;
-            for (uint32_t e = beg; e < end; ++e) {
-                uint32_t u, w;
-                arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
-                if (dist_get(S, u) + w == dv) {
-                    const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
-                    if (su == 0) {
-                        ready = false;
-                        break;
+            for (uint32_t e0 = beg; e0 < end && ready; e0 += LANE_UNROLL) {
+                uint32_t u[LANE_UNROLL], w[LANE_UNROLL], du[LANE_UNROLL];
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j) {
+                    u[j] = 0;
+                    w[j] = 0;
+                    if (e0 + j < end)
+                        arc_at<PACKED>(g.tarc, g.twt, e0 + j, g.wshift, g.wmask, u[j], w[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j)
+                    du[j] = e0 + j < end ? dist_get(S, u[j]) : BC_INF;
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j) {
+                    if (ready && e0 + j < end && du[j] + w[j] == dv) {
+                        const uint64_t su = load_u64<SCOPE>(&S.sigma[u[j]]);
+                        if (su == 0) {
+                            ready = false;
+                        } else {
+                            const uint64_t t = acc + su;
+                            ovf |= t < acc;
+                            acc = t;
+                            if (RECORD)
+                                S.preds[beg + tight] = (int32_t)u[j];
+                            ++tight;
+                        }
                     }
-                    const uint64_t t = acc + su;
-                    ovf |= t < acc;
-                    acc = t;
-                    ++tight;
                 }
             }
             if (ready) {
@@ -291,8 +331,14 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                     acc = ~0ull; // stays non-zero so dependants do not wait forever
                 }
                 store_u64<SCOPE>(&S.sigma[v], acc);
-                store_f64<SCOPE>(&S.delta[v], -1.0);
+                store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                 dag += tight;
+                if (RECORD) {
+                    S.pcnt[v] = (int32_t)tight;
+                    for (uint32_t j = 0; j < tight; ++j)
+                        __hip_atomic_fetch_add(&S.scnt[S.preds[beg + j]], 1, __ATOMIC_RELAXED,
+                                               SCOPE);
+                }
             }
             pend = !ready;
         }
@@ -311,21 +357,34 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             const uint32_t dv = dist_get(S, hv);
             uint64_t acc = 0;
             bool ready = true, ovf = false;
-            uint32_t tight = 0;
-            for (uint32_t e = hb + lane; e < he; e += WAVE) {
-                uint32_t u, w;
-                arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
-                if (dist_get(S, u) + w == dv) {
-                    const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
-                    if (su == 0) {
-                        ready = false;
-                        break;
+            uint32_t tight = 0;      // this lane's tight arcs
+            uint32_t recorded = 0;   // tight arcs of the wave so far (uniform)
+            for (uint32_t e0 = hb; e0 < he; e0 += WAVE) {
+                const uint32_t e = e0 + lane;
+                bool t = false;
+                if (e < he) {
+                    uint32_t u, w;
+                    arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
+                    if (dist_get(S, u) + w == dv) {
+                        const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                        if (su == 0) {
+                            ready = false;
+                        } else {
+                            const uint64_t x = acc + su;
+                            ovf |= x < acc;
+                            acc = x;
+                            ++tight;
+                            t = true;
+                            if (RECORD) {
+                                const uint64_t tm = __ballot(true);
+                                S.preds[hb + recorded + lanes_below(tm)] = (int32_t)u;
+                            }
+                        }
                     }
-                    const uint64_t t = acc + su;
-                    ovf |= t < acc;
-                    acc = t;
-                    ++tight;
                 }
+                recorded += (uint32_t)__popcll(__ballot(t));
+                if (__ballot(!ready))
+                    break;
             }
             const bool all_ready = __ballot(!ready) == 0;
             acc = wave_sum_u64_checked(acc, ovf);
@@ -336,9 +395,14 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                     acc = ~0ull;
                 }
                 store_u64<SCOPE>(&S.sigma[hv], acc);
-                store_f64<SCOPE>(&S.delta[hv], -1.0);
+                store_f64<SCOPE>(&S.delta[hv], RECORD ? 0.0 : -1.0);
                 dag += tight;
+                if (RECORD)
+                    S.pcnt[hv] = (int32_t)tight;
             }
+            if (RECORD && all_ready)
+                for (uint32_t j = lane; j < tight; j += WAVE)
+                    __hip_atomic_fetch_add(&S.scnt[S.preds[hb + j]], 1, __ATOMIC_RELAXED, SCOPE);
             const bool p = !all_ready && lane == 0;
             const int k = wave_alloc(c.pend_cnt, p);
             if (p)
@@ -375,17 +439,27 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             const double sv = (double)S.sigma[v];
             double acc = 0.0;
             bool ready = true;
-            for (uint32_t e = beg; e < end; ++e) {
-                uint32_t u, w;
-                arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                const uint32_t du = dist_get(S, u);
-                if (du != BC_INF && du == dv + w) {
-                    const double dl = load_f64<SCOPE>(&S.delta[u]);
-                    if (dl < 0.0) {
-                        ready = false;
-                        break;
+            for (uint32_t e0 = beg; e0 < end && ready; e0 += LANE_UNROLL) {
+                uint32_t u[LANE_UNROLL], w[LANE_UNROLL], du[LANE_UNROLL];
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j) {
+                    u[j] = 0;
+                    w[j] = 0;
+                    if (e0 + j < end)
+                        arc_at<PACKED>(g.arc, g.wt, e0 + j, g.wshift, g.wmask, u[j], w[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j)
+                    du[j] = e0 + j < end ? dist_get(S, u[j]) : BC_INF;
+#pragma unroll
+                for (int j = 0; j < LANE_UNROLL; ++j) {
+                    if (ready && du[j] != BC_INF && du[j] == dv + w[j]) {
+                        const double dl = load_f64<SCOPE>(&S.delta[u[j]]);
+                        if (dl < 0.0)
+                            ready = false;
+                        else
+                            acc += sv / (double)S.sigma[u[j]] * (1.0 + dl);
                     }
-                    acc += sv / (double)S.sigma[u] * (1.0 + dl);
                 }
             }
             if (ready) {
@@ -446,5 +520,104 @@ __device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             if (p)
                 c.pend_q[k] = hv;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dependencies by pushing along the recorded shortest-path DAG (Sec. 2.1
+// recursion, Alg. 3 evaluated in reverse topological order): a vertex whose
+// successors have all added their terms is final; it adds its dependency to
+// the centrality and pushes sigma[u] / sigma[w] * (1 + delta[w]) into every
+// recorded predecessor u, whose successor count drops by one.  A predecessor
+// whose count reaches zero joins the next frontier.
+// ---------------------------------------------------------------------------
+struct KahnCtx {
+    const int32_t *items;
+    int len;
+    int worker, nworkers;
+    int lane_max;
+    int32_t s;
+    int32_t *next_q;
+    int *next_cnt;
+    const int32_t *perm; // optional caller-indexed output
+};
+
+template <int SCOPE>
+__device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double c)
+{
+    __hip_atomic_fetch_add(&S.delta[u], c, __ATOMIC_RELAXED, SCOPE);
+    return __hip_atomic_fetch_sub(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE) == 1;
+}
+
+template <int SCOPE, bool ATOMIC_BC>
+__device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, double *bc)
+{
+#pragma clang fp contract(off)
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        int32_t w = 0;
+        uint32_t pb = 0, np = 0;
+        double dw = 0.0, sw = 1.0;
+        if (valid) {
+            w = c.items[i];
+            pb = g.trow[w];
+            np = (uint32_t)S.pcnt[w];
+            dw = load_f64<SCOPE>(&S.delta[w]);
+            sw = (double)S.sigma[w];
+            if (w != c.s) {
+                const int32_t o = c.perm ? c.perm[w] : w;
+                if (ATOMIC_BC)
+                    unsafeAtomicAdd(&bc[o], dw);
+                else
+                    bc[o] += dw;
+            }
+        }
+        const bool heavy = valid && np > (uint32_t)c.lane_max;
+        if (valid && !heavy) {
+            for (uint32_t j = 0; j < np; ++j) {
+                const int32_t u = S.preds[pb + j];
+                const bool fin = push_dependency<SCOPE>(S, u, (double)S.sigma[u] / sw * (1.0 + dw));
+                const int k = wave_alloc(c.next_cnt, fin);
+                if (fin)
+                    c.next_q[k] = u;
+            }
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hb = (uint32_t)__shfl((int)pb, l);
+            const uint32_t hn = (uint32_t)__shfl((int)np, l);
+            const double hd = __shfl(dw, l);
+            const double hs = __shfl(sw, l);
+            for (uint32_t j = lane; j < hn; j += WAVE) {
+                const int32_t u = S.preds[hb + j];
+                const bool fin = push_dependency<SCOPE>(S, u, (double)S.sigma[u] / hs * (1.0 + hd));
+                const int k = wave_alloc(c.next_cnt, fin);
+                if (fin)
+                    c.next_q[k] = u;
+            }
+        }
+    }
+}
+
+// Members with no DAG successor start the dependency pass.
+__device__ __forceinline__ void kahn_leaves(const Slab &S, const int32_t *order, int n_r, int worker,
+                                            int nworkers, int32_t *q, int *cnt)
+{
+    const int lane = lane_id();
+    for (int base = worker * WAVE; base < n_r; base += nworkers * WAVE) {
+        const int i = base + lane;
+        int32_t v = 0;
+        bool leaf = false;
+        if (i < n_r) {
+            v = order[i];
+            leaf = S.scnt[v] == 0;
+        }
+        const int k = wave_alloc(cnt, leaf);
+        if (leaf)
+            q[k] = v;
     }
 }

@@ -278,8 +278,10 @@ class HipExec {
         int H = 0, per_cu = 1;
         batched_lds_plan(g, nt, true, opts_.compute.lds_vertices, H, per_cu);
         const int fill = g->num_cus * per_cu;
-        const SlabLayout L = slab_layout(g->n);
-        int slots = opts_.slots_per_sweep ? opts_.slots_per_sweep : fill;
+        const SlabLayout L = slab_layout(g->n, g->nnz);
+        // A sweep takes a quarter of the GPU by default, so sweeps of other
+        // graphs (and of later requests) run beside it instead of behind it.
+        int slots = opts_.slots_per_sweep ? opts_.slots_per_sweep : std::max(32, fill / 4);
         const int64_t by_mem = (int64_t)(opts_.slab_bytes_per_sweep / std::max<size_t>(L.stride, 1));
         slots = (int)std::max<int64_t>(1, std::min<int64_t>(slots, by_mem));
         const int cap = opts_.items_per_sweep ? opts_.items_per_sweep : std::max(64, 2 * slots);

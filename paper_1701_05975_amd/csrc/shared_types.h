@@ -45,11 +45,15 @@ struct Slab {
     int64_t *hdr;      // [0] = last queue tag used by this slab
     uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
     int32_t H;         // number of LDS-resident distances (0 = none)
+    int32_t *scnt;     // shortest-path-DAG successors not yet accumulated (batched form)
+    int32_t *pcnt;     // number of recorded DAG predecessors of each vertex
+    int32_t *preds;    // DAG predecessors of v at preds[trow[v] ...] (in-row positions)
 };
 
 // Byte offsets of the slab arrays inside one slot (all 256-byte aligned).
 struct SlabLayout {
-    size_t d, sigma, delta, bcp, stamp, infar, order, qa, qb, fa, fb, band_off, hdr, stride;
+    size_t d, sigma, delta, bcp, stamp, infar, order, qa, qb, fa, fb, band_off, hdr, scnt, pcnt,
+        preds, stride;
 };
 
 // ---------------------------------------------------------------------------
@@ -63,4 +67,7 @@ struct SlabLayout {
 struct DevStats {
     unsigned long long reached, arcs, dag, improvements, bands, iterations, sigma_rounds,
         delta_rounds;
+    // device wall-clock ticks summed over workgroups: initialisation, frontier
+    // expansion, count rounds, dependency rounds, far-pile splits
+    unsigned long long ticks[5];
 };
