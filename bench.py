@@ -150,7 +150,7 @@ HBM_PEAK_GBS = 8000.0
 TUNED = {
     "ba100k": dict(delta=50, wg_threads=1024, lane_max_deg=32),
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
-    "grid1000": dict(delta=130, wg_threads=512, lane_max_deg=8),
+    "grid1000": dict(delta=130, wg_threads=512, lane_max_deg=8, dep_mode=2),
     "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
 }
 
@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--lane-max", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
+    ap.add_argument("--dep-mode", type=int, default=0)
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
     ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
@@ -269,6 +270,7 @@ def main():
         base = dict(delta=args.delta or pinned.get("delta", 0),
                     wg_threads=args.wg or pinned.get("wg_threads", 0),
                     lane_max_deg=args.lane_max or pinned.get("lane_max_deg", 0),
+                    dep_mode=args.dep_mode or pinned.get("dep_mode", 0),
                     batch=args.batch, accumulate=args.accumulate,
                     stream=stream.cuda_stream)
         base.update(kw)
@@ -342,7 +344,8 @@ def main():
             "workload": f"{args.config}: {WORKLOADS[args.config]}",
             "n": g.n, "m": g.m, "k": k,
             "delta": last.delta, "wg_threads": last.wg_threads, "lane_max_deg": last.lane_max_deg,
-            "batch": last.batch, "accumulate": last.accumulate,
+            "batch": last.batch, "accumulate": last.accumulate, "dep_mode": last.dep_mode,
+            "lds_vertices": last.lds_vertices,
             "reached": last.reached, "arcs_out_reached": last.arcs_out_reached,
             "dag_arcs": last.dag_arcs, "improvements": last.improvements,
             "bands": last.bands, "iterations": last.iterations,

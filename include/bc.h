@@ -124,6 +124,9 @@ typedef struct {
                              2 = device-wide FP64 atomic adds into the output */
     int32_t lds_vertices; /* batched: distances of this many highest in-degree vertices are
                              kept in LDS per source; 0 = as many as fit, -1 = none */
+    int32_t dep_mode;     /* batched dependency pass: 0 = default (1), 1 = push along the
+                             shortest-path DAG recorded by the count pass (Kahn's order),
+                             2 = pull over out-arcs band by band in reverse */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -145,7 +148,7 @@ typedef struct {
     int64_t phase_ticks[5];   /* batched form: device clock ticks summed over workgroups spent
                                  in initialisation, frontier expansion, count rounds,
                                  dependency rounds and far-pile splits */
-    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices;
+    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode;
 } bc_stats;
 
 /*

@@ -51,7 +51,8 @@ class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("lds_vertices", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("lds_vertices", ctypes.c_int32), ("dep_mode", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class bc_stats(ctypes.Structure):
@@ -65,7 +66,8 @@ class bc_stats(ctypes.Structure):
                 ("phase_ticks", ctypes.c_int64 * 5),
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
-                ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32)]
+                ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
+                ("dep_mode", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -157,11 +159,12 @@ def _ptr(a: np.ndarray):
 
 
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
-                 accumulate=0, lds_vertices=0, stream=None) -> bc_options:
+                 accumulate=0, lds_vertices=0, dep_mode=0, stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
     o.lane_max_deg, o.wg_threads, o.autotune, o.accumulate = lane_max_deg, wg_threads, autotune, accumulate
     o.lds_vertices = lds_vertices
+    o.dep_mode = dep_mode
     o.stream = stream
     return o
 

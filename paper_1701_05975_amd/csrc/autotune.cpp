@@ -72,6 +72,15 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
                 }
             }
         }
+        if (!o.dep_mode) {
+            ResolvedOptions t = c;
+            t.dep_mode = c.dep_mode == 1 ? 2 : 1;
+            const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
+            if (ms < best) {
+                best = ms;
+                c = t;
+            }
+        }
         if (!o.lane_max_deg) {
             for (int lm : {4, 8, 16, 64, 128}) {
                 ResolvedOptions t = c;
@@ -87,12 +96,15 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
         g->tuned.delta = c.delta;
         g->tuned.lane_max = c.lane_max;
         g->tuned.wg_threads = c.wg_threads;
+        g->tuned.dep_mode = c.dep_mode;
         g->tuned.best_ms_per_source = best / (double)sample;
     }
     if (!o.delta)
         r.delta = g->tuned.delta;
     if (!o.lane_max_deg)
         r.lane_max = g->tuned.lane_max;
+    if (!o.dep_mode)
+        r.dep_mode = g->tuned.dep_mode;
     if (!o.wg_threads && r.wg_threads != g->tuned.wg_threads) {
         r.wg_threads = g->tuned.wg_threads;
         int H = 0, per_cu = 1;

@@ -492,6 +492,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "negative option");
     if (o.accumulate < 0 || o.accumulate > 2)
         throw bc_error(BC_E_INVAL, "unknown accumulate mode %d", o.accumulate);
+    if (o.dep_mode < 0 || o.dep_mode > 2)
+        throw bc_error(BC_E_INVAL, "unknown dependency mode %d", o.dep_mode);
     r.mode = o.mode == BC_MODE_PLAIN ? BC_MODE_PLAIN : BC_MODE_BATCHED;
     r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
     r.wg_threads = o.wg_threads ? o.wg_threads : 256;
@@ -500,6 +502,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.delta = o.delta ? o.delta : default_delta(g);
     r.lane_max = o.lane_max_deg ? o.lane_max_deg : 32;
     r.accumulate = o.accumulate ? o.accumulate : 1;
+    r.dep_mode = o.dep_mode ? o.dep_mode : 1;
     int per_cu = 1;
     batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_vertices, per_cu);
     const int fill = g->num_cus * per_cu;
@@ -572,6 +575,7 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->wg_threads = r.wg_threads;
     st->accumulate = r.accumulate;
     st->lds_vertices = r.lds_vertices;
+    st->dep_mode = r.dep_mode;
 }
 
 static void check_device_errors(const DevCounters &c)
@@ -614,6 +618,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.iperm = g->iperm_dev();
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
+        a.kahn = r.dep_mode == 1 ? 1 : 0;
         a.delta = (uint32_t)r.delta;
         a.lane_max = r.lane_max;
         a.stats = &c->stats;

@@ -51,12 +51,13 @@ struct ResolvedOptions {
     int accumulate = 1;
     int autotune = 0;
     int lds_vertices = 0; // H: distances kept in LDS per source
+    int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
     hipStream_t stream = nullptr;
 };
 
 struct TunedOptions {
     bool valid = false;
-    int delta = 0, lane_max = 0, wg_threads = 0;
+    int delta = 0, lane_max = 0, wg_threads = 0, dep_mode = 0;
     double best_ms_per_source = 0.0;
 };
 

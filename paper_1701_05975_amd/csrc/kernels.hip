@@ -46,7 +46,7 @@ __device__ __forceinline__ void phase_mark(WgCtl &C, long long &t0, int phase)
 
 // Runs the count (or dependency) rounds over the members order[b0, b1) of
 // one band inside a workgroup.  Returns false if the round bound tripped.
-template <bool PACKED, int NT, bool SIGMA, bool ATOMIC_BC>
+template <bool PACKED, int NT, bool SIGMA, bool ATOMIC_BC, bool RECORD>
 __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const BatchArgs &a,
                                int32_t s, long long idx, int b0, int b1, double *bc,
                                uint64_t &st_arcs, uint64_t &st_dag)
@@ -75,7 +75,7 @@ __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const
         rc.item_err = a.item_err;
         rc.perm = ATOMIC_BC ? a.perm : nullptr;
         if (SIGMA)
-            sigma_round<PACKED, WG_SCOPE, true>(g, S, rc, st_arcs, st_dag);
+            sigma_round<PACKED, WG_SCOPE, RECORD>(g, S, rc, st_arcs, st_dag);
         else
             delta_round<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, rc, bc);
         __syncthreads();
@@ -155,10 +155,11 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             S.ld[v] = BC_INF;
         for (int v = S.H + tid; v < n; v += NT)
             S.d[v] = BC_INF;
-        for (int v = tid; v < n; v += NT) {
+        for (int v = tid; v < n; v += NT)
             S.sigma[v] = 0;
-            S.scnt[v] = 0;
-        }
+        if (a.kahn)
+            for (int v = tid; v < n; v += NT)
+                S.scnt[v] = 0;
         __syncthreads();
         if (tid == 0) {
             dist_set(S, s, 0);
@@ -227,8 +228,12 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             // The band is closed: its members order[b0, b1) have final distances.
             const int b0 = C.band_start, b1 = C.order_cnt;
             if (b1 > b0) {
-                if (!wg_band_rounds<PACKED, NT, true, ATOMIC_BC>(g, S, C, a, s, idx, b0, b1, bc,
-                                                                  st_arcs, st_dag)) {
+                const bool ok =
+                    a.kahn ? wg_band_rounds<PACKED, NT, true, ATOMIC_BC, true>(
+                                 g, S, C, a, s, idx, b0, b1, bc, st_arcs, st_dag)
+                           : wg_band_rounds<PACKED, NT, true, ATOMIC_BC, false>(
+                                 g, S, C, a, s, idx, b0, b1, bc, st_arcs, st_dag);
+                if (!ok) {
                     if (tid == 0)
                         C.abort = 1;
                     __syncthreads();
@@ -293,9 +298,22 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             phase_mark(C, tmark, 4);
         }
 
-        // Backward pass (Alg. 3): Kahn's order over the recorded shortest-path
-        // DAG, from the vertices without successors towards the source.
-        if (!C.abort) {
+        // Backward pass (Alg. 3), either band by band in reverse with pulls over
+        // out-arcs, or in Kahn's order over the recorded shortest-path DAG,
+        // from the vertices without successors towards the source.
+        if (!C.abort && !a.kahn) {
+            const int nb = C.nbands;
+            for (int b = nb - 1; b >= 0; --b) {
+                const int b0 = S.band_off[b], b1 = S.band_off[b + 1];
+                if (!wg_band_rounds<PACKED, NT, false, ATOMIC_BC, false>(
+                        g, S, C, a, s, idx, b0, b1, bc, st_arcs, st_dag)) {
+                    if (tid == 0)
+                        C.abort = 1;
+                    break;
+                }
+            }
+        }
+        if (!C.abort && a.kahn) {
             if (tid == 0)
                 C.pend_cnt = 0;
             __syncthreads();

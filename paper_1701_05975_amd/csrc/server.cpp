@@ -175,6 +175,7 @@ class HipExec {
         a.iperm = g->iperm_dev();
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
+        a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.delta = (uint32_t)delta_for(g);
         a.lane_max = lane_max_for(g);
         a.stats = &dc->stats;
@@ -263,6 +264,12 @@ class HipExec {
         if (opts_.compute.lane_max_deg)
             return opts_.compute.lane_max_deg;
         return g->tuned.valid ? g->tuned.lane_max : 32;
+    }
+    int dep_mode_for(bc_graph *g) const
+    {
+        if (opts_.compute.dep_mode)
+            return opts_.compute.dep_mode;
+        return g->tuned.valid && g->tuned.dep_mode ? g->tuned.dep_mode : 1;
     }
     int wg_for(bc_graph *g) const
     {

@@ -33,6 +33,8 @@ OPTION_SETS = [
     dict(mode=bc.BC_MODE_PLAIN, delta=1, lane_max_deg=1),
     dict(lds_vertices=-1),
     dict(lds_vertices=5, wg_threads=256),
+    dict(dep_mode=2),
+    dict(dep_mode=2, accumulate=2, lane_max_deg=1),
 ]
 
 
