@@ -230,6 +230,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--dep-mode", type=int, default=0)
+    ap.add_argument("--edges", action="store_true",
+                    help="time node + edge betweenness (bc_compute_edges_device)")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
     ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
@@ -259,10 +261,17 @@ def main():
 
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    G = bc.Graph(g)
+    G = bc.Graph(g, edges=args.edges)
     src_dev = torch.from_numpy(sources).to("cuda")
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    eout = torch.empty(max(g.nnz, 1), dtype=torch.float64, device="cuda") if args.edges else None
     k = int(len(sources))
+
+    def run(o):
+        if args.edges:
+            return bc.bc_compute_edges_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(),
+                                              eout.data_ptr(), o)
+        return bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
 
     pinned = {} if args.autotune else TUNED.get(args.config, {})
 
@@ -279,7 +288,7 @@ def main():
     # warm-up (with --autotune the first call searches and caches the settings)
     o = opts(autotune=1 if args.autotune else 0)
     for i in range(args.warmup):
-        st = bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
+        st = run(o)
         print(f"# warmup {i}: {st.ms:.1f} ms (delta={st.delta} wg={st.wg_threads} "
               f"lane_max={st.lane_max_deg} batch={st.batch})", file=sys.stderr, flush=True)
 
@@ -287,7 +296,7 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
-        st = bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
+        st = run(o)
         stats.append(st)
         print(f"# step {i}: {st.ms:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -311,7 +320,7 @@ def main():
     }
 
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and not args.edges:
         ps = sources[: min(args.plain_sources, k)]
         ps_dev = torch.from_numpy(np.ascontiguousarray(ps)).to("cuda")
         po = opts(mode=bc.BC_MODE_PLAIN)
@@ -328,7 +337,8 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(g, sources, args.cpu_sources)
 
     rec = {
-        "metric": "weighted-BC GTEPS (sources x m / s), batched",
+        "metric": ("weighted node+edge BC GTEPS (sources x m / s), batched" if args.edges
+                   else "weighted-BC GTEPS (sources x m / s), batched"),
         "value": round(gteps, 4),
         "unit": "GTEPS",
         "n_gpus": 1,

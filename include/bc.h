@@ -61,6 +61,8 @@ typedef enum {
 #define BC_KEEP_ORDER 2u /* keep the caller's vertex numbering on the device; by default a
                             graph whose in-degrees are skewed is renumbered internally by
                             decreasing in-degree (results are always in the caller's ids) */
+#define BC_EDGE_BC 4u    /* prepare edge betweenness (bc_compute_edges*): a 4-byte map per
+                            arc is kept on the device */
 
 typedef struct bc_graph bc_graph;
 typedef struct bc_result bc_result;
@@ -178,6 +180,28 @@ bc_status bc_compute(bc_graph *g, const int32_t *sources, int64_t k, const bc_op
  */
 bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
                             const bc_options *opt, double *bc_dev, bc_stats *stats);
+
+/*
+ * Edge betweenness (the paper's tool reports node and edge BC, Sec. 1): for
+ * every arc e = (v, u) of the caller's CSR, ebc[e] = sum over the listed
+ * sources s and all targets t of sigma_st(e) / sigma_st, where sigma_st(e)
+ * counts the shortest s-t paths that use the arc; equivalently the sum over s
+ * of sigma_sv / sigma_su * (1 + delta_s(u)) when e lies on a shortest path
+ * from s.  For an undirected graph the two arcs of an edge are reported
+ * separately (their sum is the edge's value).  Node centralities are returned
+ * as well.  The graph must have been created with BC_EDGE_BC; the batched form
+ * is used (BC_E_INVAL for BC_MODE_PLAIN), with the recorded-DAG dependency pass.
+ *
+ * bc_compute_edges: host source list (NULL with k = n for all vertices), host
+ * outputs bc_host[n] (may be NULL) and ebc_host[nnz].
+ * bc_compute_edges_device: device source list and device outputs bc_dev[n],
+ * ebc_dev[nnz]; stats may be NULL.
+ */
+bc_status bc_compute_edges(bc_graph *g, const int32_t *sources, int64_t k, const bc_options *opt,
+                           double *bc_host, double *ebc_host);
+bc_status bc_compute_edges_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
+                                  const bc_options *opt, double *bc_dev, double *ebc_dev,
+                                  bc_stats *stats);
 
 /* Copy a result's centralities to host memory bc_host[n]. */
 bc_status bc_result_bc(const bc_result *r, double *bc_host);

@@ -8,6 +8,7 @@ from .oracle import (  # noqa: F401
     SigmaOverflow,
     build,
     oracle_bc,
+    oracle_bc_edges,
     oracle_source_state,
     lib_path,
 )

@@ -223,7 +223,7 @@ static int forward_pass(int32_t n, const int64_t *row_ptr, const int32_t *col, c
  * are final.  Terms are summed in arc order.
  */
 static void backward_pass(const int64_t *row_ptr, const int32_t *col, const int32_t *w,
-                          workspace *ws, int32_t n_order)
+                          workspace *ws, int32_t n_order, double *ebc)
 {
     const int64_t *d = ws->d;
     const uint64_t *sigma = ws->sigma;
@@ -233,8 +233,14 @@ static void backward_pass(const int64_t *row_ptr, const int32_t *col, const int3
         double acc = 0.0;
         for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             int32_t u = col[e];
-            if (d[u] != DIST_INF && d[u] == d[v] + (int64_t)w[e])
-                acc += ((double)sigma[v] / (double)sigma[u]) * (1.0 + delta[u]);
+            if (d[u] != DIST_INF && d[u] == d[v] + (int64_t)w[e]) {
+                double term = ((double)sigma[v] / (double)sigma[u]) * (1.0 + delta[u]);
+                acc += term;
+                /* edge betweenness: the same term is the dependency of source s
+                   on the arc e = (v, u) (the tool's edge BC, Sec. 1) */
+                if (ebc)
+                    ebc[e] += term;
+            }
         }
         delta[v] = acc;
     }
@@ -261,7 +267,7 @@ int oracle_source_state(int32_t n, int64_t nnz, const int64_t *row_ptr, const in
     if (rc == ORACLE_OK) {
         for (int32_t v = 0; v < n; ++v)
             ws.delta[v] = 0.0;
-        backward_pass(row_ptr, col, w, &ws, cnt);
+        backward_pass(row_ptr, col, w, &ws, cnt, NULL);
         memcpy(d_out, ws.d, (size_t)n * sizeof(int64_t));
         memcpy(sigma_out, ws.sigma, (size_t)n * sizeof(uint64_t));
         memcpy(delta_out, ws.delta, (size_t)n * sizeof(double));
@@ -285,6 +291,7 @@ typedef struct {
     const int32_t *sources;
     int64_t lo, hi;         /* this thread's slice of the source list */
     double *bc;             /* this thread's partial [n] */
+    double *ebc;            /* this thread's partial edge betweenness [nnz], or NULL */
     int64_t first_bad;      /* smallest source-list index that overflowed, or -1 */
     int rc;
 } thread_job;
@@ -309,7 +316,7 @@ static void *bc_thread(void *arg)
             job->rc = ORACLE_SIGMA_OVERFLOW;
             continue;
         }
-        backward_pass(job->row_ptr, job->col, job->w, &ws, cnt);
+        backward_pass(job->row_ptr, job->col, job->w, &ws, cnt, job->ebc);
         for (int32_t j = 0; j < cnt; ++j) {
             int32_t v = ws.order[j];
             if (v != s)
@@ -322,14 +329,18 @@ static void *bc_thread(void *arg)
 
 /*
  * bc[v] = sum over the k listed sources s (with repetition) of delta_s(v),
- * v != s.  Sources are split into contiguous slices, one per thread; the
- * per-thread partial sums are added in thread order, so the result is
- * deterministic for a fixed thread count.  *first_bad receives the smallest
- * source-list index whose path counts overflowed (or -1).
+ * v != s; when ebc is not NULL, ebc[e] receives the edge betweenness of every
+ * arc e = (v, u): the sum over the sources of sigma_sv / sigma_su * (1 +
+ * delta_s(u)) when e lies on a shortest path from s, i.e. the number of
+ * shortest s-t paths through e divided by sigma_st, summed over all t.
+ * Sources are split into contiguous slices, one per thread; the per-thread
+ * partial sums are added in thread order, so the result is deterministic for
+ * a fixed thread count.  *first_bad receives the smallest source-list index
+ * whose path counts overflowed (or -1).
  */
-int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
-              const int32_t *w, const int32_t *sources, int64_t k, int32_t threads, double *bc,
-              int64_t *first_bad)
+int oracle_bc_edges(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                    const int32_t *w, const int32_t *sources, int64_t k, int32_t threads,
+                    double *bc, double *ebc, int64_t *first_bad)
 {
     int rc = oracle_check_graph(n, nnz, row_ptr, col, w);
     if (rc != ORACLE_OK)
@@ -343,6 +354,9 @@ int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col
         threads = (int32_t)k;
     for (int32_t v = 0; v < n; ++v)
         bc[v] = 0.0;
+    if (ebc)
+        for (int64_t e = 0; e < nnz; ++e)
+            ebc[e] = 0.0;
     if (first_bad)
         *first_bad = -1;
     if (k == 0)
@@ -351,10 +365,13 @@ int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col
     thread_job *jobs = calloc((size_t)threads, sizeof(thread_job));
     pthread_t *tid = calloc((size_t)threads, sizeof(pthread_t));
     double *part = calloc((size_t)threads * (size_t)(n > 0 ? n : 1), sizeof(double));
-    if (!jobs || !tid || !part) {
+    double *epart = ebc ? calloc((size_t)threads * (size_t)(nnz > 0 ? nnz : 1), sizeof(double))
+                        : NULL;
+    if (!jobs || !tid || !part || (ebc && !epart)) {
         free(jobs);
         free(tid);
         free(part);
+        free(epart);
         return ORACLE_NOMEM;
     }
     for (int32_t t = 0; t < threads; ++t) {
@@ -367,6 +384,7 @@ int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col
         jobs[t].lo = k * t / threads;
         jobs[t].hi = k * (t + 1) / threads;
         jobs[t].bc = part + (size_t)t * (size_t)n;
+        jobs[t].ebc = epart ? epart + (size_t)t * (size_t)nnz : NULL;
     }
     for (int32_t t = 1; t < threads; ++t)
         pthread_create(&tid[t], NULL, bc_thread, &jobs[t]);
@@ -385,11 +403,22 @@ int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col
             bad = jobs[t].first_bad;
         for (int32_t v = 0; v < n; ++v)
             bc[v] += jobs[t].bc[v];
+        if (ebc)
+            for (int64_t e = 0; e < nnz; ++e)
+                ebc[e] += jobs[t].ebc[e];
     }
     if (first_bad)
         *first_bad = bad;
     free(jobs);
     free(tid);
     free(part);
+    free(epart);
     return rc;
+}
+
+int oracle_bc(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+              const int32_t *w, const int32_t *sources, int64_t k, int32_t threads, double *bc,
+              int64_t *first_bad)
+{
+    return oracle_bc_edges(n, nnz, row_ptr, col, w, sources, k, threads, bc, NULL, first_bad);
 }

@@ -61,6 +61,9 @@ def _bind(lib):
     lib.oracle_bc.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, ctypes.c_int64,
                               ctypes.c_int32, P, P]
     lib.oracle_bc.restype = ctypes.c_int
+    lib.oracle_bc_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, ctypes.c_int64,
+                                     ctypes.c_int32, P, P, P]
+    lib.oracle_bc_edges.restype = ctypes.c_int
     lib.oracle_source_state.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, ctypes.c_int32,
                                         P, P, P, P]
     lib.oracle_source_state.restype = ctypes.c_int
@@ -94,6 +97,25 @@ def oracle_bc(g, sources, threads: int | None = None, lib: str | None = None) ->
     if rc != 0:
         raise OracleError(f"oracle_bc failed with code {rc}")
     return bc[: g.n]
+
+
+def oracle_bc_edges(g, sources, threads: int | None = None, lib: str | None = None):
+    """(BC float64[n], edge betweenness float64[nnz] in CSR arc order) over the sources."""
+    L = _lib(lib)
+    rp, col, w = _graph_arrays(g)
+    src = np.ascontiguousarray(np.asarray(sources), dtype=np.int32)
+    bc = np.zeros(max(g.n, 1), dtype=np.float64)
+    ebc = np.zeros(max(col.shape[0], 1), dtype=np.float64)
+    bad = ctypes.c_int64(-1)
+    if threads is None:
+        threads = min(os.cpu_count() or 1, 16)
+    rc = L.oracle_bc_edges(g.n, col.shape[0], _ptr(rp), _ptr(col), _ptr(w), _ptr(src),
+                           src.shape[0], threads, _ptr(bc), _ptr(ebc), ctypes.byref(bad))
+    if rc == 1:
+        raise SigmaOverflow(bad.value)
+    if rc != 0:
+        raise OracleError(f"oracle_bc_edges failed with code {rc}")
+    return bc[: g.n], ebc[: col.shape[0]]
 
 
 def oracle_source_state(g, s: int, lib: str | None = None):

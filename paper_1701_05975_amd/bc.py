@@ -35,6 +35,7 @@ STATUS_NAMES = {
 
 BC_DIRECTED = 1
 BC_KEEP_ORDER = 2
+BC_EDGE_BC = 4
 BC_MODE_AUTO, BC_MODE_BATCHED, BC_MODE_PLAIN = 0, 1, 2
 
 INT32_MAX = 2**31 - 1
@@ -121,6 +122,9 @@ def _load():
         "bc_compute": ([P, P, i64, ctypes.POINTER(bc_options), ctypes.POINTER(P)], ctypes.c_int),
         "bc_compute_device": ([P, P, i64, ctypes.POINTER(bc_options), P,
                                ctypes.POINTER(bc_stats)], ctypes.c_int),
+        "bc_compute_edges": ([P, P, i64, ctypes.POINTER(bc_options), P, P], ctypes.c_int),
+        "bc_compute_edges_device": ([P, P, i64, ctypes.POINTER(bc_options), P, P,
+                                     ctypes.POINTER(bc_stats)], ctypes.c_int),
         "bc_result_bc": ([P, P], ctypes.c_int),
         "bc_result_device_ptr": ([P, ctypes.POINTER(P)], ctypes.c_int),
         "bc_result_stats": ([P, ctypes.POINTER(bc_stats)], ctypes.c_int),
@@ -213,6 +217,30 @@ def bc_compute_device(g, sources_dev_ptr: int, k: int, bc_dev_ptr: int,
     return st
 
 
+def bc_compute_edges(g, sources, n: int, nnz: int, options: bc_options | None = None):
+    """(bc float64[n], edge betweenness float64[nnz] in CSR arc order)."""
+    opt = ctypes.byref(options) if options is not None else None
+    bc = np.empty(max(n, 1), dtype=np.float64)
+    ebc = np.empty(max(nnz, 1), dtype=np.float64)
+    if sources is None:
+        _check(_lib.bc_compute_edges(g, None, int(n), opt, _ptr(bc), _ptr(ebc)))
+    else:
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        _check(_lib.bc_compute_edges(g, _ptr(s) if s.size else None, int(s.shape[0]), opt,
+                                     _ptr(bc), _ptr(ebc)))
+    return bc[:n], ebc[:nnz]
+
+
+def bc_compute_edges_device(g, sources_dev_ptr: int, k: int, bc_dev_ptr: int, ebc_dev_ptr: int,
+                            options: bc_options | None = None) -> bc_stats:
+    st = bc_stats()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.bc_compute_edges_device(g, ctypes.c_void_p(sources_dev_ptr), int(k), opt,
+                                        ctypes.c_void_p(bc_dev_ptr), ctypes.c_void_p(ebc_dev_ptr),
+                                        ctypes.byref(st)))
+    return st
+
+
 def bc_result_bc(r, n: int) -> np.ndarray:
     out = np.empty(max(n, 1), dtype=np.float64)
     _check(_lib.bc_result_bc(r, _ptr(out)))
@@ -257,11 +285,12 @@ def bc_version() -> str:
 class Graph:
     """Owning wrapper of a bc_graph handle built from a CSR graph object."""
 
-    def __init__(self, csr, keep_order: bool = False):
+    def __init__(self, csr, keep_order: bool = False, edges: bool = False):
         self.n = int(csr.n)
         self.m = int(csr.m)
         self.csr = csr
         flags = (BC_DIRECTED if csr.directed else 0) | (BC_KEEP_ORDER if keep_order else 0)
+        flags |= BC_EDGE_BC if edges else 0
         self.handle = bc_create_graph(csr.n, csr.row_ptr, csr.col, csr.w, flags)
 
     def info(self) -> dict:
@@ -275,6 +304,11 @@ class Graph:
             return bc_result_bc(r, self.n), bc_result_stats(r).as_dict()
         finally:
             bc_destroy_result(r)
+
+    def edge_bc(self, sources=None, **opts):
+        """(bc float64[n], edge betweenness float64[nnz]) over a host source list."""
+        return bc_compute_edges(self.handle, sources, self.n, int(self.csr.nnz),
+                                make_options(**opts))
 
     def source_state(self, s: int, **opts):
         return bc_source_state(self.handle, s, self.n, make_options(**opts))

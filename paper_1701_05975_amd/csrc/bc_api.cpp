@@ -118,7 +118,8 @@ static int bit_width_u64(uint64_t x)
 // ---------------------------------------------------------------------------
 static void build_transpose(int32_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *w, std::vector<int64_t> &trow,
-                            std::vector<int32_t> &tcol, std::vector<int32_t> &tw)
+                            std::vector<int32_t> &tcol, std::vector<int32_t> &tw,
+                            std::vector<uint32_t> *tsrc = nullptr)
 {
     const int64_t nnz = row_ptr[n];
     trow.assign((size_t)n + 1, 0);
@@ -129,12 +130,50 @@ static void build_transpose(int32_t n, const int64_t *row_ptr, const int32_t *co
     std::vector<int64_t> pos(trow.begin(), trow.end() - 1);
     tcol.resize((size_t)nnz);
     tw.resize((size_t)nnz);
+    if (tsrc)
+        tsrc->resize((size_t)nnz);
     for (int32_t u = 0; u < n; ++u)
         for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
             const int64_t p = pos[(size_t)col[e]]++;
             tcol[(size_t)p] = u;
             tw[(size_t)p] = w[e];
+            if (tsrc)
+                (*tsrc)[(size_t)p] = (uint32_t)e; // the arc this in-arc entry stands for
         }
+}
+
+// For a symmetric (undirected) CSR: rev[e] = index of the reverse arc of e
+// (equal weight); parallel arcs are paired in the order they appear.
+static std::vector<uint32_t> reverse_arcs(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                                          const int32_t *w)
+{
+    struct Key {
+        int32_t a, b, w;
+        uint32_t pos;
+        bool operator<(const Key &o) const
+        {
+            if (a != o.a)
+                return a < o.a;
+            if (b != o.b)
+                return b < o.b;
+            if (w != o.w)
+                return w < o.w;
+            return pos < o.pos;
+        }
+    };
+    const int64_t nnz = row_ptr[n];
+    std::vector<Key> fwd((size_t)nnz), bwd((size_t)nnz);
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            fwd[(size_t)e] = Key{u, col[e], w[e], (uint32_t)e};
+            bwd[(size_t)e] = Key{col[e], u, w[e], (uint32_t)e};
+        }
+    std::sort(fwd.begin(), fwd.end());
+    std::sort(bwd.begin(), bwd.end());
+    std::vector<uint32_t> rev((size_t)nnz);
+    for (size_t i = 0; i < fwd.size(); ++i)
+        rev[fwd[i].pos] = bwd[i].pos;
+    return rev;
 }
 
 // Undirected input must list every edge in both directions with one weight:
@@ -206,8 +245,9 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
         throw bc_error(BC_E_INVAL, "nnz must be below 2^32 - 1");
     if (!row_ptr || (nnz > 0 && (!col || !w)))
         throw bc_error(BC_E_INVAL, "null CSR array");
-    if (flags & ~(BC_DIRECTED | BC_KEEP_ORDER))
-        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~(BC_DIRECTED | BC_KEEP_ORDER));
+    const uint32_t known = BC_DIRECTED | BC_KEEP_ORDER | BC_EDGE_BC;
+    if (flags & ~known)
+        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~known);
     if (row_ptr[0] != 0 || row_ptr[n] != nnz)
         throw bc_error(BC_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
     int64_t maxdeg = 0;
@@ -291,28 +331,38 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
             });
         }
     }
+    // Device numbering: the caller's or the renumbered one; ce[e] is the
+    // caller's index of device arc e (needed only for edge betweenness).
+    const bool want_edges = (flags & BC_EDGE_BC) != 0;
+    std::vector<int64_t> rrow;
+    std::vector<int32_t> rcol, rw;
+    std::vector<uint32_t> ce;
+    const int64_t *irow = row_ptr;
+    const int32_t *icol = col, *iw = w;
     if (!order.empty()) {
         g->renumbered = true;
         g->host_iperm.assign((size_t)n, 0);
         for (int32_t v = 0; v < n; ++v)
             g->host_iperm[(size_t)order[(size_t)v]] = v;
-        std::vector<int64_t> rrow((size_t)n + 1, 0);
-        std::vector<int32_t> rcol((size_t)nnz), rw((size_t)nnz);
+        rrow.assign((size_t)n + 1, 0);
+        rcol.resize((size_t)nnz);
+        rw.resize((size_t)nnz);
+        if (want_edges)
+            ce.resize((size_t)nnz);
         for (int32_t v = 0; v < n; ++v) {
             const int32_t o = order[(size_t)v];
             int64_t at = rrow[(size_t)v];
             for (int64_t e = row_ptr[o]; e < row_ptr[o + 1]; ++e, ++at) {
                 rcol[(size_t)at] = g->host_iperm[(size_t)col[e]];
                 rw[(size_t)at] = w[e];
+                if (want_edges)
+                    ce[(size_t)at] = (uint32_t)e;
             }
             rrow[(size_t)v + 1] = at;
         }
-        upload_arcs(g.get(), n, rrow.data(), rcol.data(), rw.data(), g->row, g->arc, g->wt);
-        if (directed) {
-            build_transpose(n, rrow.data(), rcol.data(), rw.data(), trow, tcol, tw);
-            upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc,
-                        g->twt);
-        }
+        irow = rrow.data();
+        icol = rcol.data();
+        iw = rw.data();
         g->perm.alloc((size_t)n * 4);
         g->iperm.alloc((size_t)n * 4);
         hip_check(hipMemcpy(g->perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice),
@@ -320,12 +370,30 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
         hip_check(hipMemcpy(g->iperm.p, g->host_iperm.data(), (size_t)n * 4,
                             hipMemcpyHostToDevice),
                   "upload numbering");
-    } else {
-        upload_arcs(g.get(), n, row_ptr, col, w, g->row, g->arc, g->wt);
-        if (directed)
-            upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc,
-                        g->twt);
     }
+    upload_arcs(g.get(), n, irow, icol, iw, g->row, g->arc, g->wt);
+    std::vector<uint32_t> tsrc;
+    if (directed) {
+        if (!order.empty() || want_edges)
+            build_transpose(n, irow, icol, iw, trow, tcol, tw, want_edges ? &tsrc : nullptr);
+        upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc, g->twt);
+    }
+    if (want_edges && nnz > 0) {
+        // The dependency pass records a DAG arc u -> w at a position p of w's
+        // in-row; emap[p] is the caller's index of that arc.
+        std::vector<uint32_t> emap((size_t)nnz);
+        std::vector<uint32_t> rev;
+        if (!directed)
+            rev = reverse_arcs(n, irow, icol, iw);
+        for (int64_t p = 0; p < nnz; ++p) {
+            const uint32_t dev_arc = directed ? tsrc[(size_t)p] : rev[(size_t)p];
+            emap[(size_t)p] = ce.empty() ? dev_arc : ce[dev_arc];
+        }
+        g->emap.alloc((size_t)nnz * 4);
+        hip_check(hipMemcpy(g->emap.p, emap.data(), (size_t)nnz * 4, hipMemcpyHostToDevice),
+                  "upload arc map");
+    }
+    g->edges_ready = want_edges;
     g->dnode.alloc((size_t)n * sizeof(int32_t));
     g->deg.alloc((size_t)n * sizeof(int32_t));
     hip_check(launch_graph_vertex_info(g->view(), g->packed, (int32_t *)g->dnode.p,
@@ -591,7 +659,7 @@ static void check_device_errors(const DevCounters &c)
 }
 
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
-                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms)
+                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms, double *ebc_dev)
 {
     hipStream_t st = r.stream;
     ensure_slabs(g, g->batched, r.batch, st);
@@ -599,6 +667,9 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
     const bool atomic_bc = r.accumulate == 2;
     if (atomic_bc || k == 0)
         hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
+    if (ebc_dev)
+        hip_check(launch_fill_u64((unsigned long long *)ebc_dev, (size_t)g->nnz, 0ull, st),
+                  "zero");
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
@@ -619,6 +690,8 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
         a.kahn = r.dep_mode == 1 ? 1 : 0;
+        a.ebc = ebc_dev;
+        a.emap = (const uint32_t *)g->emap.p;
         a.delta = (uint32_t)r.delta;
         a.lane_max = r.lane_max;
         a.stats = &c->stats;
@@ -736,9 +809,18 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
 }
 
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
-                    const bc_options *opt, double *bc_dev, bc_stats *stats)
+                    const bc_options *opt, double *bc_dev, bc_stats *stats, double *ebc_dev)
 {
     ResolvedOptions r = resolve_options(g, opt, k);
+    if (ebc_dev) {
+        // edge betweenness comes from the recorded-DAG dependency pass
+        if (!g->edges_ready)
+            throw bc_error(BC_E_INVAL, "the graph was created without BC_EDGE_BC");
+        if (r.mode == BC_MODE_PLAIN)
+            throw bc_error(BC_E_INVAL, "edge betweenness needs the batched form");
+        r.dep_mode = 1;
+        r.autotune = 0;
+    }
     if (r.autotune && r.mode == BC_MODE_BATCHED && k > 0)
         autotune(g, r, opt, src_dev, k);
     DevCounters cnt;
@@ -761,7 +843,7 @@ void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host
         kms = ms;
         launches = 0;
     } else {
-        run_batched(g, r, src_dev, k, bc_dev, cnt, ms, &kms);
+        run_batched(g, r, src_dev, k, bc_dev, cnt, ms, &kms, ebc_dev);
         launches = k > 0 ? 1 : 0;
     }
     check_device_errors(cnt);
@@ -851,6 +933,66 @@ bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
         if (k < 0)
             throw bc_error(BC_E_INVAL, "k must be >= 0");
         compute_device(g, sources_dev, nullptr, k, opt, bc_dev, stats);
+    });
+}
+
+bc_status bc_compute_edges_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
+                                  const bc_options *opt, double *bc_dev, double *ebc_dev,
+                                  bc_stats *stats)
+{
+    return guarded([&] {
+        if (!g || !bc_dev || !ebc_dev || (k > 0 && !sources_dev))
+            throw bc_error(BC_E_INVAL, "null argument");
+        if (k < 0)
+            throw bc_error(BC_E_INVAL, "k must be >= 0");
+        if (g->nnz == 0) {
+            compute_device(g, sources_dev, nullptr, k, opt, bc_dev, stats);
+            return;
+        }
+        compute_device(g, sources_dev, nullptr, k, opt, bc_dev, stats, ebc_dev);
+    });
+}
+
+bc_status bc_compute_edges(bc_graph *g, const int32_t *sources, int64_t k, const bc_options *opt,
+                           double *bc_host, double *ebc_host)
+{
+    return guarded([&] {
+        if (!g || !ebc_host)
+            throw bc_error(BC_E_INVAL, "null argument");
+        if (k < 0)
+            throw bc_error(BC_E_INVAL, "k must be >= 0");
+        std::vector<int32_t> all;
+        if (!sources) {
+            if (k != g->n && k != 0)
+                throw bc_error(BC_E_INVAL, "sources may be NULL only with k = n");
+            all.resize((size_t)k);
+            for (int64_t i = 0; i < k; ++i)
+                all[(size_t)i] = (int32_t)i;
+            sources = all.data();
+        }
+        for (int64_t i = 0; i < k; ++i)
+            if (sources[i] < 0 || sources[i] >= g->n)
+                throw bc_error(BC_E_INVAL, "sources[%lld] = %d out of range", (long long)i,
+                               sources[i]);
+        ResolvedOptions r = resolve_options(g, opt, k);
+        ensure_sources(g, k);
+        if (k > 0)
+            hip_check(hipMemcpyAsync(g->src_buf.p, sources, (size_t)k * 4, hipMemcpyHostToDevice,
+                                     r.stream),
+                      "upload sources");
+        DevBuf bc, ebc;
+        bc.alloc((size_t)g->n * 8);
+        ebc.alloc((size_t)std::max<int64_t>(g->nnz, 1) * 8);
+        if (g->nnz == 0)
+            hip_check(launch_fill_u64((unsigned long long *)ebc.p, 1, 0ull, r.stream), "zero");
+        compute_device(g, (const int32_t *)g->src_buf.p, sources, k, opt, (double *)bc.p, nullptr,
+                       g->nnz ? (double *)ebc.p : nullptr);
+        hip_check(hipStreamSynchronize(r.stream), "synchronize");
+        if (bc_host)
+            hip_check(hipMemcpy(bc_host, bc.p, (size_t)g->n * 8, hipMemcpyDeviceToHost), "copy");
+        if (g->nnz)
+            hip_check(hipMemcpy(ebc_host, ebc.p, (size_t)g->nnz * 8, hipMemcpyDeviceToHost),
+                      "copy");
     });
 }
 

@@ -81,6 +81,8 @@ struct bc_graph {
     DevBuf trow, tarc, twt; // in-arcs (directed graphs only)
     DevBuf dnode, deg;      // per-vertex minimum out-weight and out-degree
     DevBuf perm, iperm;     // internal -> caller id, caller -> internal id (when renumbered)
+    DevBuf emap;            // in-row position -> caller arc index (edge betweenness)
+    bool edges_ready = false;
     std::vector<int32_t> host_iperm;
     DevBuf ctl;             // DevCounters
     DevBuf plain_ctl;       // PlainCtl
@@ -121,8 +123,10 @@ void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, 
                       int &per_cu);
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
-                    const bc_options *opt, double *bc_dev, bc_stats *stats);
+                    const bc_options *opt, double *bc_dev, bc_stats *stats,
+                    double *ebc_dev = nullptr);
 void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int32_t *src_dev,
               int64_t k);
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
-                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms);
+                 double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms,
+                 double *ebc_dev = nullptr);

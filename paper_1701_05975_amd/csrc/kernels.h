@@ -21,6 +21,8 @@ struct BatchArgs {
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
+    double *ebc;                  // optional edge betweenness output (caller arc order)
+    const uint32_t *emap;         // in-row position -> caller arc index
     uint32_t delta;               // band width
     int lane_max;
     DevStats *stats;

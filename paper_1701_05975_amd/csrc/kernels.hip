@@ -343,7 +343,9 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 kc.next_q = which ? S.qa : S.qb;
                 kc.next_cnt = &C.pend_cnt;
                 kc.perm = ATOMIC_BC ? a.perm : nullptr;
-                kahn_step<WG_SCOPE, ATOMIC_BC>(g, S, kc, bc);
+                kc.ebc = a.ebc;
+                kc.emap = a.emap;
+                kahn_step<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, kc, bc);
                 __syncthreads();
                 len = C.pend_cnt;
                 __syncthreads();

@@ -261,10 +261,11 @@ __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 // weights >= 1 every such u has d[u] < d[v], so it belongs to this band or
 // an earlier one.
 //
-// With RECORD, the tight in-arcs of v are also written to preds[trow[v] ..]
-// (the slice of v's own in-row, so no allocation is needed), pcnt[v] holds
-// their number and every recorded predecessor's successor count scnt is
-// incremented once v is final; the dependency pass then walks this DAG.
+// With RECORD, the in-row positions of the tight in-arcs of v are also
+// written to preds[trow[v] ..] (the slice of v's own in-row, so no allocation
+// is needed), pcnt[v] holds their number and every recorded predecessor's
+// successor count scnt is incremented once v is final; the dependency pass
+// then walks this DAG.
 template <bool PACKED, int SCOPE, bool RECORD>
 __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
@@ -318,8 +319,8 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                             const uint64_t t = acc + su;
                             ovf |= t < acc;
                             acc = t;
-                            if (RECORD)
-                                S.preds[beg + tight] = (int32_t)u[j];
+                            if (RECORD) // the in-row position identifies the DAG arc
+                                S.preds[beg + tight] = (int32_t)(e0 + j);
                             ++tight;
                         }
                     }
@@ -335,9 +336,12 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                 dag += tight;
                 if (RECORD) {
                     S.pcnt[v] = (int32_t)tight;
-                    for (uint32_t j = 0; j < tight; ++j)
-                        __hip_atomic_fetch_add(&S.scnt[S.preds[beg + j]], 1, __ATOMIC_RELAXED,
-                                               SCOPE);
+                    for (uint32_t j = 0; j < tight; ++j) {
+                        uint32_t u, w;
+                        arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[beg + j], g.wshift,
+                                       g.wmask, u, w);
+                        __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+                    }
                 }
             }
             pend = !ready;
@@ -377,7 +381,7 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                             t = true;
                             if (RECORD) {
                                 const uint64_t tm = __ballot(true);
-                                S.preds[hb + recorded + lanes_below(tm)] = (int32_t)u;
+                                S.preds[hb + recorded + lanes_below(tm)] = (int32_t)e;
                             }
                         }
                     }
@@ -401,8 +405,12 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                     S.pcnt[hv] = (int32_t)tight;
             }
             if (RECORD && all_ready)
-                for (uint32_t j = lane; j < tight; j += WAVE)
-                    __hip_atomic_fetch_add(&S.scnt[S.preds[hb + j]], 1, __ATOMIC_RELAXED, SCOPE);
+                for (uint32_t j = lane; j < tight; j += WAVE) {
+                    uint32_t u, w;
+                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[hb + j], g.wshift, g.wmask,
+                                   u, w);
+                    __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+                }
             const bool p = !all_ready && lane == 0;
             const int k = wave_alloc(c.pend_cnt, p);
             if (p)
@@ -540,6 +548,8 @@ struct KahnCtx {
     int32_t *next_q;
     int *next_cnt;
     const int32_t *perm; // optional caller-indexed output
+    double *ebc;         // optional edge betweenness (caller arc order)
+    const uint32_t *emap; // in-row position -> caller arc index
 };
 
 template <int SCOPE>
@@ -549,7 +559,7 @@ __device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double
     return __hip_atomic_fetch_sub(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE) == 1;
 }
 
-template <int SCOPE, bool ATOMIC_BC>
+template <bool PACKED, int SCOPE, bool ATOMIC_BC>
 __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, double *bc)
 {
 #pragma clang fp contract(off)
@@ -577,8 +587,14 @@ __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, do
         const bool heavy = valid && np > (uint32_t)c.lane_max;
         if (valid && !heavy) {
             for (uint32_t j = 0; j < np; ++j) {
-                const int32_t u = S.preds[pb + j];
-                const bool fin = push_dependency<SCOPE>(S, u, (double)S.sigma[u] / sw * (1.0 + dw));
+                const uint32_t pos = (uint32_t)S.preds[pb + j];
+                uint32_t uu, wgt;
+                arc_at<PACKED>(g.tarc, g.twt, pos, g.wshift, g.wmask, uu, wgt);
+                const int32_t u = (int32_t)uu;
+                const double term = (double)S.sigma[u] / sw * (1.0 + dw);
+                if (c.ebc) // the term is the source's dependency on the arc u -> w
+                    unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
+                const bool fin = push_dependency<SCOPE>(S, u, term);
                 const int k = wave_alloc(c.next_cnt, fin);
                 if (fin)
                     c.next_q[k] = u;
@@ -593,8 +609,14 @@ __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, do
             const double hd = __shfl(dw, l);
             const double hs = __shfl(sw, l);
             for (uint32_t j = lane; j < hn; j += WAVE) {
-                const int32_t u = S.preds[hb + j];
-                const bool fin = push_dependency<SCOPE>(S, u, (double)S.sigma[u] / hs * (1.0 + hd));
+                const uint32_t pos = (uint32_t)S.preds[hb + j];
+                uint32_t uu, wgt;
+                arc_at<PACKED>(g.tarc, g.twt, pos, g.wshift, g.wmask, uu, wgt);
+                const int32_t u = (int32_t)uu;
+                const double term = (double)S.sigma[u] / hs * (1.0 + hd);
+                if (c.ebc)
+                    unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
+                const bool fin = push_dependency<SCOPE>(S, u, term);
                 const int k = wave_alloc(c.next_cnt, fin);
                 if (fin)
                     c.next_q[k] = u;

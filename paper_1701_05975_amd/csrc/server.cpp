@@ -176,6 +176,8 @@ class HipExec {
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
+        a.ebc = nullptr;
+        a.emap = nullptr;
         a.delta = (uint32_t)delta_for(g);
         a.lane_max = lane_max_for(g);
         a.stats = &dc->stats;

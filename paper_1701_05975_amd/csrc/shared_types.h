@@ -47,7 +47,7 @@ struct Slab {
     int32_t H;         // number of LDS-resident distances (0 = none)
     int32_t *scnt;     // shortest-path-DAG successors not yet accumulated (batched form)
     int32_t *pcnt;     // number of recorded DAG predecessors of each vertex
-    int32_t *preds;    // DAG predecessors of v at preds[trow[v] ...] (in-row positions)
+    int32_t *preds;    // in-row positions of v's DAG in-arcs, at preds[trow[v] ...]
 };
 
 // Byte offsets of the slab arrays inside one slot (all 256-byte aligned).

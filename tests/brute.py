@@ -158,3 +158,34 @@ def hop_invariant(g, sources):
             H[t] = h
             total += Fraction(h, S[s][t]) - 1
     return total
+
+
+def enumerate_ebc(g, sources=None):
+    """Edge betweenness by literal enumeration of shortest paths as arc
+    sequences (parallel arcs are distinct): for every ordered pair (s, t) and
+    every arc e, the fraction of shortest s-t paths that use e."""
+    out = [[] for _ in range(g.n)]
+    for v in range(g.n):
+        for e in range(int(g.row_ptr[v]), int(g.row_ptr[v + 1])):
+            out[v].append((int(g.col[e]), int(g.w[e]), e))
+    ebc = [Fraction(0)] * g.nnz
+    srcs = range(g.n) if sources is None else sources
+    for s in srcs:
+        best = {}
+        stack = [(s, 0, (), frozenset([s]))]
+        while stack:
+            v, L, arcs, seen = stack.pop()
+            if v != s:
+                cur = best.get(v)
+                if cur is None or L < cur[0]:
+                    best[v] = (L, [arcs])
+                elif L == cur[0]:
+                    cur[1].append(arcs)
+            for (u, w, e) in out[v]:
+                if u not in seen:
+                    stack.append((u, L + w, arcs + (e,), seen | {u}))
+        for t, (L, paths) in best.items():
+            for p in paths:
+                for e in p:
+                    ebc[e] += Fraction(1, len(paths))
+    return ebc

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from brute import enumerate_bc, hop_invariant, pairwise_bc
+from brute import enumerate_bc, enumerate_ebc, hop_invariant, pairwise_bc
 from paper_1701_05975_amd import graphgen as gg
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -251,3 +251,49 @@ def test_thread_count_does_not_change_result_beyond_rounding():
     a = oracle.oracle_bc(g, srcs, threads=1)
     b = oracle.oracle_bc(g, srcs, threads=5)
     assert np.allclose(a, b, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- edge betweenness
+
+@pytest.mark.parametrize("g", small_cases()[:6], ids=lambda g: g.name + str(g.meta.get("seed")))
+def test_edge_bc_matches_literal_enumeration(g):
+    want = enumerate_ebc(g)
+    bc, ebc = oracle.oracle_bc_edges(g, np.arange(g.n), threads=2)
+    for e in range(g.nnz):
+        assert close(ebc[e], want[e]), (e, ebc[e], float(want[e]))
+    assert np.allclose(bc, oracle.oracle_bc(g, np.arange(g.n)), rtol=1e-14, atol=0)
+
+
+def test_edge_bc_parallel_arcs_are_distinct_paths():
+    g = gg.csr_from_arcs(3, [0, 0, 1], [1, 1, 2], [2, 2, 1], directed=True)
+    _, ebc = oracle.oracle_bc_edges(g, np.arange(3))
+    want = enumerate_ebc(g)
+    assert [float(x) for x in want] == list(ebc)
+    assert ebc[0] == ebc[1] == 1.0  # each parallel arc carries half of 0->1 and of 0->2
+
+
+@pytest.mark.parametrize("n", [2, 6, 40])
+def test_edge_bc_path_and_star_closed_forms(n):
+    rng = np.random.default_rng(n)
+    g = gg.path_graph(n, rng.integers(1, 100, size=n - 1))
+    _, ebc = oracle.oracle_bc_edges(g, np.arange(n))
+    for v in range(n):
+        for e in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            u = int(g.col[e])
+            i = min(u, v)  # the edge {i, i+1}
+            assert ebc[e] == (i + 1) * (n - 1 - i)
+    g = gg.star_graph(n, rng.integers(1, 100, size=n - 1))
+    _, ebc = oracle.oracle_bc_edges(g, np.arange(n))
+    assert np.all(ebc == n - 1)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_bc_sum_is_bc_sum_plus_reached_pairs(seed):
+    g = gg.random_graph(50, 0.08, 1, 3, seed=500 + seed, directed=bool(seed % 2))
+    srcs = np.arange(0, 50, 2)
+    bc, ebc = oracle.oracle_bc_edges(g, srcs)
+    pairs = 0
+    for s in srcs:
+        d, _, _, nr = oracle.oracle_source_state(g, int(s))
+        pairs += nr - 1
+    assert close(ebc.sum(), bc.sum() + pairs, 1e-12)
