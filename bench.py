@@ -33,6 +33,9 @@ WORKLOADS = {
                 "k=1024 sampled sources",
     "rmat22": "directed R-MAT scale 22 (a,b,c=.57,.19,.19; self-loops/duplicates dropped), "
               "w uniform [1,255], k=1024 sampled sources",
+    "ablation": "thread-mapping variants on ER and Kronecker graphs n=2^14..2^18 (avg deg 32) "
+                "and n=2^17 (avg deg 4), degree sweeps on ER n=20000 and Kronecker 2^15 (avg deg 4..64), "
+                "w uniform [1,10], 256 sampled sources per graph",
     "serving": "8 resident graphs (ER n=10k/500k deg 8 w[1,100]; BA n=50k/1M m=5 w[1,1000]; "
                "grid 100x100/1414x1414 -2% w[1,255]; R-MAT scale 14/21 w[1,255]); Poisson "
                "arrivals; each request k-sampled BC, k log-uniform in [64,4096]",
@@ -51,6 +54,73 @@ def serving_graphs():
         gg.rmat_graph(14, 16 << 14, .57, .19, .19, 1, 255, seed=107),
         gg.rmat_graph(21, 16 << 21, .57, .19, .19, 1, 255, seed=108),
     ]
+
+
+ABLATION_VARIANTS = [
+    # (name, options) -- the paper's four thread mappings (Sec. 3.3-3.4, Figs. 3-5)
+    # recast for 64-lane waves, plus the adaptive default of this library
+    ("node-parallel, thread per vertex", dict(node_parallel=1, virtual_warp=1)),
+    ("node-parallel, warp 32", dict(node_parallel=1, virtual_warp=32)),
+    ("work-efficient, thread per vertex", dict(virtual_warp=1)),
+    ("work-efficient, warp 4", dict(virtual_warp=4)),
+    ("work-efficient, warp 8", dict(virtual_warp=8)),
+    ("work-efficient, warp 16", dict(virtual_warp=16)),
+    ("work-efficient, warp 32", dict(virtual_warp=32)),
+    ("work-efficient, wave 64", dict(virtual_warp=64)),
+    ("work-efficient, adaptive lane/wave", dict()),
+]
+
+
+def run_ablation(args):
+    """Thread-mapping ablation on the paper's synthetic families (Sec. 4.2):
+    ER and Kronecker graphs, n = 2^14..2^18 at average degree 32, n = 2^17 at
+    average degree 4, and degree sweeps on ER n = 20000 and Kronecker 2^15;
+    weights uniform in [1, 10] (Sec. 4.1).  Every variant
+    runs the same sources with the same other settings."""
+    import torch
+    from paper_1701_05975_amd import bc, graphgen as gg
+
+    # (family, n, edge factor = half the average degree); sizes first, then the
+    # degree sweeps (Figs. 4-5)
+    specs = []
+    for sc in range(14, 19):
+        specs += [("er", 1 << sc, 16), ("kron", 1 << sc, 16)]
+    specs += [("er", 1 << 17, 2), ("kron", 1 << 17, 2)]
+    for ef in (2, 4, 8, 32):
+        specs += [("er", 20_000, ef), ("kron", 1 << 15, ef)]
+    rows = []
+    stream = torch.cuda.current_stream()
+    for gi, (fam, n, ef) in enumerate(specs):
+        sc = n.bit_length() - 1
+        g = (gg.er_graph(n, ef * n, 1, 10, seed=300 + gi) if fam == "er"
+             else gg.kronecker_graph(sc, ef, 1, 10, seed=400 + gi))
+        srcs = gg.sample_sources(g, args.ablation_sources, seed=500 + gi)
+        G = bc.Graph(g)
+        s_dev = torch.from_numpy(srcs).to("cuda")
+        out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        ref = None
+        for name, extra in ABLATION_VARIANTS:
+            o = bc.make_options(wg_threads=1024, stream=stream.cuda_stream, **extra)
+            bc.bc_compute_device(G.handle, s_dev.data_ptr(), len(srcs), out.data_ptr(), o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = bc.bc_compute_device(G.handle, s_dev.data_ptr(), len(srcs), out.data_ptr(), o)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            res = out.cpu().numpy()
+            if ref is None:
+                ref = res
+            nz = ref != 0
+            dev = float(np.max(np.abs(res[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+            assert dev <= 1e-9 and np.all(res[~nz] == 0), (name, dev)
+            row = {"graph": f"{fam} n={n} avg deg {2 * ef}", "m": g.m, "variant": name,
+                   "gteps": round(len(srcs) * g.m / t / 1e9, 4), "ms": round(t * 1e3, 2),
+                   "iterations_per_source": round(st.iterations / len(srcs), 1)}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+        G.close()
+    print(json.dumps({"metric": "thread-mapping ablation, weighted-BC GTEPS (batched form)",
+                      "sources_per_graph": args.ablation_sources, "rows": rows}), flush=True)
 
 
 def run_serving(args):
@@ -148,7 +218,7 @@ HBM_PEAK_GBS = 8000.0
 # (python bench.py --autotune prints them); pinned so that the timed and the
 # profiled command launch identical kernels.
 TUNED = {
-    "ba100k": dict(delta=50, wg_threads=1024, lane_max_deg=32),
+    "ba100k": dict(delta=100, wg_threads=1024, lane_max_deg=32),
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
     "grid1000": dict(delta=130, wg_threads=512, lane_max_deg=8, dep_mode=2),
     "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
@@ -232,6 +302,7 @@ def main():
     ap.add_argument("--dep-mode", type=int, default=0)
     ap.add_argument("--edges", action="store_true",
                     help="time node + edge betweenness (bc_compute_edges_device)")
+    ap.add_argument("--ablation-sources", type=int, default=256)
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
     ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
@@ -247,6 +318,9 @@ def main():
     ensure_built()
     if args.config == "serving":
         run_serving(args)
+        return
+    if args.config == "ablation":
+        run_ablation(args)
         return
     import torch
 

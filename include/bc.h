@@ -129,6 +129,12 @@ typedef struct {
     int32_t dep_mode;     /* batched dependency pass: 0 = default (1), 1 = push along the
                              shortest-path DAG recorded by the count pass (Kahn's order),
                              2 = pull over out-arcs band by band in reverse */
+    int32_t virtual_warp; /* frontier expansion: 0 = one lane per vertex up to lane_max_deg
+                             arcs, a whole wave above; 1, 2, 4, ..., 64 = a fixed group of that
+                             many lanes per vertex (the warp-centric mapping of Sec. 3.4) */
+    int32_t node_parallel;/* batched frontier expansion: 0 = over the queue (work-efficient,
+                             Sec. 3.3); 1 = over every vertex, expanding those queued
+                             (node-parallel, Alg. 2) -- for comparison only */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -150,7 +156,8 @@ typedef struct {
     int64_t phase_ticks[5];   /* batched form: device clock ticks summed over workgroups spent
                                  in initialisation, frontier expansion, count rounds,
                                  dependency rounds and far-pile splits */
-    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode;
+    int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode,
+        virtual_warp, node_parallel;
 } bc_stats;
 
 /*

@@ -53,6 +53,7 @@ class bc_options(ctypes.Structure):
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("accumulate", ctypes.c_int32),
                 ("lds_vertices", ctypes.c_int32), ("dep_mode", ctypes.c_int32),
+                ("virtual_warp", ctypes.c_int32), ("node_parallel", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -68,7 +69,8 @@ class bc_stats(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("delta", ctypes.c_int32),
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
-                ("dep_mode", ctypes.c_int32)]
+                ("dep_mode", ctypes.c_int32), ("virtual_warp", ctypes.c_int32),
+                ("node_parallel", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -163,12 +165,15 @@ def _ptr(a: np.ndarray):
 
 
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
-                 accumulate=0, lds_vertices=0, dep_mode=0, stream=None) -> bc_options:
+                 accumulate=0, lds_vertices=0, dep_mode=0, virtual_warp=0, node_parallel=0,
+                 stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
     o.lane_max_deg, o.wg_threads, o.autotune, o.accumulate = lane_max_deg, wg_threads, autotune, accumulate
     o.lds_vertices = lds_vertices
     o.dep_mode = dep_mode
+    o.virtual_warp = virtual_warp
+    o.node_parallel = node_parallel
     o.stream = stream
     return o
 

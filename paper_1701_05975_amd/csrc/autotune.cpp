@@ -30,9 +30,10 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
         o = *opt;
     if (!g->tuned.valid) {
         const int fill = r.batch;
-        int64_t sample = std::min<int64_t>(k, std::max<int64_t>(2 * (int64_t)fill, 64));
-        // keep each trial short on large graphs: at most ~4e9 arc-sources
-        while (sample > 64 && (double)sample * (double)std::max<int64_t>(g->nnz, 1) > 4e9)
+        // one full occupancy of sources, so that each trial runs the GPU in the
+        // regime of the real call; on large graphs at most ~2e10 arc-sources
+        int64_t sample = std::min<int64_t>(k, std::max<int64_t>((int64_t)fill, 64));
+        while (sample > 64 && (double)sample * (double)std::max<int64_t>(g->nnz, 1) > 2e10)
             sample /= 2;
         DevBuf scratch;
         scratch.alloc((size_t)g->n * sizeof(double));
@@ -43,10 +44,23 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
         double best = time_candidate(g, c, src_dev, sample, (double *)scratch.p);
 
         if (!o.delta) {
+            // coarse factors of the default band width, then a finer step around the winner
             const int d0 = c.delta;
             for (double f : {0.125, 0.25, 0.5, 2.0, 4.0, 8.0}) {
                 ResolvedOptions t = c;
                 t.delta = std::max(1, (int)(d0 * f));
+                const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
+                if (ms < best) {
+                    best = ms;
+                    c = t;
+                }
+            }
+            const int d1 = c.delta;
+            for (double f : {0.7, 1.4}) {
+                ResolvedOptions t = c;
+                t.delta = std::max(1, (int)(d1 * f));
+                if (t.delta == d1)
+                    continue;
                 const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
                 if (ms < best) {
                     best = ms;

@@ -462,20 +462,17 @@ SlabLayout slab_layout(int32_t n, int64_t pred_slots)
         return at;
     };
     L.d = take(4 * nn);
-    L.sigma = take(8 * nn);
-    L.delta = take(8 * nn);
+    L.rec = take(VREC_BYTES * nn);
     L.bcp = take(8 * nn);
-    L.stamp = take(4 * nn);
-    L.infar = take(4 * nn);
     L.order = take(4 * nn);
     L.qa = take(4 * nn);
     L.qb = take(4 * nn);
     L.fa = take(4 * nn);
     L.fb = take(4 * nn);
+    L.oa = take(4 * nn);
+    L.ob = take(4 * nn);
     L.band_off = take(4 * (nn + 2));
     L.hdr = take(64);
-    L.scnt = take(4 * nn);
-    L.pcnt = take(4 * nn);
     L.preds = take(4 * (size_t)std::max<int64_t>(pred_slots, 1));
     L.stride = o;
     return L;
@@ -562,6 +559,10 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "unknown accumulate mode %d", o.accumulate);
     if (o.dep_mode < 0 || o.dep_mode > 2)
         throw bc_error(BC_E_INVAL, "unknown dependency mode %d", o.dep_mode);
+    if (o.virtual_warp < 0 || o.virtual_warp > 64 || (o.virtual_warp & (o.virtual_warp - 1)))
+        throw bc_error(BC_E_INVAL, "virtual_warp must be 0 or a power of two up to 64");
+    if (o.node_parallel < 0 || o.node_parallel > 1)
+        throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
     r.mode = o.mode == BC_MODE_PLAIN ? BC_MODE_PLAIN : BC_MODE_BATCHED;
     r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
     r.wg_threads = o.wg_threads ? o.wg_threads : 256;
@@ -571,6 +572,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.lane_max = o.lane_max_deg ? o.lane_max_deg : 32;
     r.accumulate = o.accumulate ? o.accumulate : 1;
     r.dep_mode = o.dep_mode ? o.dep_mode : 1;
+    r.vw = o.virtual_warp;
+    r.node_parallel = o.node_parallel;
     int per_cu = 1;
     batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_vertices, per_cu);
     const int fill = g->num_cus * per_cu;
@@ -644,6 +647,8 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->accumulate = r.accumulate;
     st->lds_vertices = r.lds_vertices;
     st->dep_mode = r.dep_mode;
+    st->virtual_warp = r.vw;
+    st->node_parallel = r.node_parallel;
 }
 
 static void check_device_errors(const DevCounters &c)
@@ -690,6 +695,8 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
         a.kahn = r.dep_mode == 1 ? 1 : 0;
+        a.vw = r.vw;
+        a.node_parallel = r.node_parallel;
         a.ebc = ebc_dev;
         a.emap = (const uint32_t *)g->emap.p;
         a.delta = (uint32_t)r.delta;
@@ -726,6 +733,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
     PlainArgs a;
     a.g = g->view();
+    a.vw = r.vw;
     a.perm = g->perm_dev();
     a.slab_base = (char *)g->plain.base.p;
     a.L = g->plain.L;
@@ -751,7 +759,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     // with the same band width and lane threshold.
     const int PLAIN_GRAPH_PAIRS = 32;
     if (!g->plain_exec || g->plain_exec_delta != a.delta || g->plain_exec_lane_max != a.lane_max ||
-        g->plain_exec_slab != (const void *)a.slab_base) {
+        g->plain_exec_vw != a.vw || g->plain_exec_slab != (const void *)a.slab_base) {
         if (g->plain_exec) {
             (void)hipGraphExecDestroy(g->plain_exec);
             g->plain_exec = nullptr;
@@ -768,6 +776,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
         hip_check(ie, "instantiate");
         g->plain_exec_delta = a.delta;
         g->plain_exec_lane_max = a.lane_max;
+        g->plain_exec_vw = a.vw;
         g->plain_exec_slab = (const void *)a.slab_base;
     }
     const unsigned long long iter_cap = 8ull * (unsigned long long)g->n + 1024ull;

@@ -52,6 +52,8 @@ struct ResolvedOptions {
     int autotune = 0;
     int lds_vertices = 0; // H: distances kept in LDS per source
     int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
+    int vw = 0;           // expansion lanes per vertex (0 adaptive)
+    int node_parallel = 0;
     hipStream_t stream = nullptr;
 };
 
@@ -95,6 +97,7 @@ struct bc_graph {
     hipGraphExec_t plain_exec = nullptr;
     uint32_t plain_exec_delta = 0;
     int plain_exec_lane_max = 0;
+    int plain_exec_vw = 0;
     const void *plain_exec_slab = nullptr;
 
     Workspace batched, plain;

@@ -22,27 +22,54 @@ __device__ __forceinline__ void arc_at(const uint32_t *arc, const int32_t *wt, u
     }
 }
 
+// One field of the per-vertex records, indexed like an array.
+template <typename T, int OFF>
+struct VField {
+    char *rec;
+    __device__ __forceinline__ T &operator[](int64_t v) const
+    {
+        return *reinterpret_cast<T *>(rec + v * VREC_BYTES + OFF);
+    }
+};
+
+struct Slab {
+    uint32_t *d;       // tentative / final distance, BC_INF = unreached
+    VField<int32_t, VREC_STAMP> stamp;
+    VField<int32_t, VREC_INFAR> infar;
+    VField<int32_t, VREC_SCNT> scnt;
+    VField<uint64_t, VREC_SIGMA> sigma;
+    VField<double, VREC_DELTA> delta;
+    double *bcp;       // per-slab partial centrality (batched form)
+    int32_t *order;    // members of each band, band after band
+    int32_t *qa, *qb;  // near queues / pending lists
+    int32_t *fa, *fb;  // inner far piles (distance below the pile bound)
+    int32_t *oa, *ob;  // outer far piles (distance at or above the pile bound)
+    int32_t *band_off; // band b = order[band_off[b] .. band_off[b+1])
+    int64_t *hdr;      // [0] = last queue tag used by this slab
+    uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
+    int32_t H;         // number of LDS-resident distances (0 = none)
+    int32_t *preds;    // in-row positions of v's DAG in-arcs, at preds[trow[v] ...],
+                       // ended by -1 when fewer than the in-degree
+};
+
 __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slot)
 {
     char *p = base + (size_t)slot * L.stride;
     Slab s;
     s.d = (uint32_t *)(p + L.d);
-    s.sigma = (uint64_t *)(p + L.sigma);
-    s.delta = (double *)(p + L.delta);
+    s.stamp.rec = s.infar.rec = s.scnt.rec = s.sigma.rec = s.delta.rec = p + L.rec;
     s.bcp = (double *)(p + L.bcp);
-    s.stamp = (int32_t *)(p + L.stamp);
-    s.infar = (int32_t *)(p + L.infar);
     s.order = (int32_t *)(p + L.order);
     s.qa = (int32_t *)(p + L.qa);
     s.qb = (int32_t *)(p + L.qb);
     s.fa = (int32_t *)(p + L.fa);
     s.fb = (int32_t *)(p + L.fb);
+    s.oa = (int32_t *)(p + L.oa);
+    s.ob = (int32_t *)(p + L.ob);
     s.band_off = (int32_t *)(p + L.band_off);
     s.hdr = (int64_t *)(p + L.hdr);
     s.ld = nullptr;
     s.H = 0;
-    s.scnt = (int32_t *)(p + L.scnt);
-    s.pcnt = (int32_t *)(p + L.pcnt);
     s.preds = (int32_t *)(p + L.preds);
     return s;
 }

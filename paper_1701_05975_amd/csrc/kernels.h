@@ -21,6 +21,8 @@ struct BatchArgs {
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
+    int32_t vw;                   // expansion: 0 adaptive lane/wave, else lanes per vertex
+    int32_t node_parallel;        // expansion scans every vertex instead of the queue
     double *ebc;                  // optional edge betweenness output (caller arc order)
     const uint32_t *emap;         // in-row position -> caller arc index
     uint32_t delta;               // band width
@@ -47,6 +49,7 @@ struct PlainCtl {
 
 struct PlainArgs {
     DevGraph g;
+    int32_t vw;                   // expansion mapping, as in BatchArgs
     const int32_t *perm;          // internal id -> caller id (null: identity)
     char *slab_base;
     SlabLayout L;

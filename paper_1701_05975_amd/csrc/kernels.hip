@@ -19,11 +19,22 @@
 // ---------------------------------------------------------------------------
 // Batched form
 // ---------------------------------------------------------------------------
+// Far values this many band widths or more beyond the threshold wait in the
+// outer pile, which is scanned only when the threshold passes its bound.
+#define OUTER_BANDS 16
+
+__device__ __forceinline__ uint32_t sat_add_u32(uint32_t x, uint64_t y)
+{
+    const uint64_t t = (uint64_t)x + y;
+    return t > BC_INF ? BC_INF : (uint32_t)t;
+}
+
 struct WgCtl {
     int near_len, next_cnt, order_cnt, far_cnt, kept_cnt, pend_cnt;
-    int cur, fcur;
+    int outer_cnt, okept_cnt, resplit;
+    int cur, fcur, ocur;
     int32_t gen, band_gen;
-    uint32_t thr, thr_old, far_min;
+    uint32_t thr, thr_old, far_min, bound, outer_min;
     int band_start, nbands;
     int abort;
     long long src_idx;
@@ -175,9 +186,13 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             C.next_cnt = 0;
             C.order_cnt = 1;
             C.far_cnt = 0;
+            C.outer_cnt = 0;
+            C.ocur = 0;
             C.band_gen = C.gen;
             C.thr = a.delta;
             C.far_min = BC_INF;
+            C.outer_min = BC_INF;
+            C.bound = sat_add_u32(a.delta, (uint64_t)OUTER_BANDS * a.delta);
             C.band_start = 0;
             C.nbands = 0;
             C.abort = 0;
@@ -192,6 +207,9 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ExpandCtx ec;
                 ec.items = C.cur ? S.qb : S.qa;
                 ec.len = C.near_len;
+                ec.all_vertices = a.node_parallel;
+                ec.cur_tag = C.gen;
+                ec.vw = a.vw;
                 ec.worker = tid / WAVE;
                 ec.nworkers = NT / WAVE;
                 ec.thr = C.thr;
@@ -204,11 +222,17 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ec.order_cnt = &C.order_cnt;
                 ec.far_q = C.fcur ? S.fb : S.fa;
                 ec.far_cnt = &C.far_cnt;
-                uint32_t fmin = BC_INF;
-                expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, st_imp);
+                ec.bound = C.bound;
+                ec.outer_q = C.ocur ? S.ob : S.oa;
+                ec.outer_cnt = &C.outer_cnt;
+                uint32_t fmin = BC_INF, omin = BC_INF;
+                expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, omin, st_imp);
                 fmin = wave_min_u32(fmin);
+                omin = wave_min_u32(omin);
                 if (lane == 0 && fmin != BC_INF)
                     atomicMin(&C.far_min, fmin);
+                if (lane == 0 && omin != BC_INF)
+                    atomicMin(&C.outer_min, omin);
                 __syncthreads();
                 if (tid == 0) {
                     C.cur ^= 1;
@@ -249,25 +273,58 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.band_start = b1;
             }
             __syncthreads();
-            if (C.far_cnt == 0)
+            if (C.far_cnt == 0 && C.outer_cnt == 0)
                 break;
             // Next band: threshold from the least far distance seen.
             if (tid == 0) {
                 C.thr_old = C.thr;
-                const uint32_t lo = C.far_min > C.thr ? C.far_min : C.thr;
-                const uint64_t t = (uint64_t)lo + a.delta;
-                C.thr = t > BC_INF ? BC_INF : (uint32_t)t;
+                const uint32_t fm = C.far_min < C.outer_min ? C.far_min : C.outer_min;
+                const uint32_t lo = fm > C.thr ? fm : C.thr;
+                C.thr = sat_add_u32(lo, (uint64_t)a.delta);
                 C.far_min = BC_INF;
                 C.gen += 1;
                 C.band_gen = C.gen;
                 C.near_len = 0;
                 C.kept_cnt = 0;
+                C.okept_cnt = 0;
+                C.resplit = C.thr > C.bound && C.outer_cnt > 0;
+                if (C.thr > C.bound) {
+                    C.bound = sat_add_u32(C.thr, (uint64_t)OUTER_BANDS * a.delta);
+                    if (C.resplit)
+                        C.outer_min = BC_INF;
+                }
                 if (++C.iters > iter_cap)
                     C.abort = 1;
             }
             __syncthreads();
             if (C.abort)
                 break;
+            if (C.resplit) {
+                // the threshold passed the bound: bring the outer pile's entries
+                // below the new bound into the inner pile
+                OuterSplitCtx op;
+                op.outer_in = C.ocur ? S.ob : S.oa;
+                op.len = C.outer_cnt;
+                op.worker = tid / WAVE;
+                op.nworkers = NT / WAVE;
+                op.thr_old = C.thr_old;
+                op.bound = C.bound;
+                op.inner_q = C.fcur ? S.fb : S.fa;
+                op.inner_cnt = &C.far_cnt;
+                op.outer_out = C.ocur ? S.oa : S.ob;
+                op.kept_cnt = &C.okept_cnt;
+                uint32_t kmin = BC_INF;
+                outer_split_pass(S, op, kmin);
+                kmin = wave_min_u32(kmin);
+                if (lane == 0 && kmin != BC_INF)
+                    atomicMin(&C.outer_min, kmin);
+                __syncthreads();
+                if (tid == 0) {
+                    C.ocur ^= 1;
+                    C.outer_cnt = C.okept_cnt;
+                }
+                __syncthreads();
+            }
             {
                 SplitCtx sp;
                 sp.far_in = C.fcur ? S.fb : S.fa;
@@ -536,6 +593,9 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ExpandCtx ec;
         ec.items = c->cur ? S.qb : S.qa;
         ec.len = c->near_len;
+        ec.all_vertices = 0;
+        ec.cur_tag = c->gen;
+        ec.vw = a.vw;
         ec.worker = worker;
         ec.nworkers = nworkers;
         ec.thr = c->thr;
@@ -548,9 +608,12 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.order_cnt = &c->order_cnt;
         ec.far_q = c->fcur ? S.fb : S.fa;
         ec.far_cnt = &c->far_cnt;
-        uint32_t fmin = BC_INF;
+        ec.bound = BC_INF; // one far pile: the whole grid scans it per band
+        ec.outer_q = nullptr;
+        ec.outer_cnt = nullptr;
+        uint32_t fmin = BC_INF, omin = BC_INF;
         uint64_t imp = 0;
-        expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, imp);
+        expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, omin, imp);
         fmin = wave_min_u32(fmin);
         unsigned long long x = imp;
         for (int o = 32; o > 0; o >>= 1)

@@ -34,6 +34,12 @@ __device__ __forceinline__ int atomic_xchg_i32(int32_t *p, int32_t v)
 }
 
 template <int SCOPE>
+__device__ __forceinline__ int atomic_or_i32(int32_t *p, int32_t v)
+{
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
 __device__ __forceinline__ uint64_t load_u64(const uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE);
@@ -65,11 +71,16 @@ __device__ __forceinline__ void store_f64(double *p, double v)
 // keeps the least.  A lane that lowered d[u] below the band threshold puts u
 // in the next near queue (once per queue, by tag) and, the first time in this
 // band, in the band's member list; a lower value at or above the threshold
-// sends u to the far pile (once, by flag).
+// sends u to the far pile (once, by flag): the inner pile below the pile
+// bound, else the outer pile, which is only scanned when the threshold
+// passes the bound.
 // ---------------------------------------------------------------------------
 struct ExpandCtx {
     const int32_t *items;
     int len;
+    int all_vertices;     // node-parallel: scan every vertex, expand those queued now
+    int32_t cur_tag;      // tag of the queue being expanded (node-parallel filter)
+    int vw;               // 0: lane or wave by degree; else a fixed group of vw lanes
     int worker, nworkers; // wave index and wave count over the item list
     uint32_t thr;         // band threshold: d < thr is near
     int32_t tag_next;     // tag of the queue being filled
@@ -81,6 +92,9 @@ struct ExpandCtx {
     int *order_cnt;
     int32_t *far_q;
     int *far_cnt;
+    uint32_t bound;       // far values at or above go to the outer pile (BC_INF: none)
+    int32_t *outer_q;
+    int *outer_cnt;
 };
 
 // Arcs handled per step by a lane that walks its own row: their heads and
@@ -90,23 +104,27 @@ struct ExpandCtx {
 
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
-                                      uint32_t du, uint32_t &far_min, uint64_t &nimp)
+                                      uint32_t du, uint32_t &far_min, uint32_t &outer_min,
+                                      uint64_t &nimp)
 {
     bool imp = false;
     if (nd < du) {
         uint32_t old = dist_min<SCOPE>(S, u, nd);
         imp = nd < old;
     }
-    bool pn = false, pm = false, pf = false;
+    bool pn = false, pm = false, pf = false, po = false;
     if (imp) {
         ++nimp;
         if (nd < c.thr) {
             int32_t ot = atomic_xchg_i32<SCOPE>(&S.stamp[u], c.tag_next);
             pn = ot != c.tag_next;
             pm = ot < c.band_gen;
-        } else {
+        } else if (nd < c.bound) {
             far_min = nd < far_min ? nd : far_min;
-            pf = atomic_xchg_i32<SCOPE>(&S.infar[u], 1) == 0;
+            pf = (atomic_or_i32<SCOPE>(&S.infar[u], 1) & 1) == 0;
+        } else {
+            outer_min = nd < outer_min ? nd : outer_min;
+            po = (atomic_or_i32<SCOPE>(&S.infar[u], 2) & 2) == 0;
         }
     }
     if (__ballot(imp)) {
@@ -119,23 +137,70 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
         k = wave_alloc(c.far_cnt, pf);
         if (pf)
             c.far_q[k] = (int32_t)u;
+        if (__ballot(po)) {
+            k = wave_alloc(c.outer_cnt, po);
+            if (po)
+                c.outer_q[k] = (int32_t)u;
+        }
+    }
+}
+
+// Fixed virtual-warp mapping (Sec. 3.4): a group of vw lanes per vertex,
+// striding over its arcs; vw = 1 is one thread per vertex, vw = 64 one wave.
+template <bool PACKED, int SCOPE>
+__device__ void expand_pass_vw(const DevGraph &g, const Slab &S, const ExpandCtx &c,
+                               uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
+{
+    const int W = c.vw;
+    const int groups = WAVE / W;
+    const int lane = lane_id(), grp = lane / W, sub = lane % W;
+    const int len = c.all_vertices ? g.n : c.len;
+    for (int base = c.worker * groups; base < len; base += c.nworkers * groups) {
+        const int i = base + grp;
+        bool valid = i < len;
+        int v = 0;
+        if (valid) {
+            v = c.all_vertices ? i : c.items[i];
+            if (c.all_vertices)
+                valid = S.stamp[v] == c.cur_tag;
+        }
+        uint32_t beg = 0, end = 0, dv = BC_INF;
+        if (valid) {
+            beg = g.row[v];
+            end = g.row[v + 1];
+            dv = dist_get(S, v);
+        }
+        for (uint32_t e = beg + sub; e < end; e += W) {
+            uint32_t u, w;
+            arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+            relax<SCOPE>(S, c, u, dv + w, dist_get(S, u), far_min, outer_min, nimp);
+        }
     }
 }
 
 template <bool PACKED, int SCOPE>
 __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c,
-                            uint32_t &far_min, uint64_t &nimp)
+                            uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
 {
+    if (c.vw > 0) {
+        expand_pass_vw<PACKED, SCOPE>(g, S, c, far_min, outer_min, nimp);
+        return;
+    }
     const int lane = lane_id();
-    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+    const int len = c.all_vertices ? g.n : c.len;
+    for (int base = c.worker * WAVE; base < len; base += c.nworkers * WAVE) {
         const int i = base + lane;
-        const bool valid = i < c.len;
+        bool valid = i < len;
         uint32_t beg = 0, end = 0, dv = BC_INF;
         if (valid) {
-            const int v = c.items[i];
-            beg = g.row[v];
-            end = g.row[v + 1];
-            dv = dist_get(S, v);
+            const int v = c.all_vertices ? i : c.items[i];
+            if (c.all_vertices)
+                valid = S.stamp[v] == c.cur_tag;
+            if (valid) {
+                beg = g.row[v];
+                end = g.row[v + 1];
+                dv = dist_get(S, v);
+            }
         }
         const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
         if (valid && !heavy) {
@@ -154,7 +219,7 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
 #pragma unroll
                 for (int j = 0; j < LANE_UNROLL; ++j)
                     if (e0 + j < end)
-                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], far_min, nimp);
+                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], far_min, outer_min, nimp);
             }
         }
         uint64_t hm = __ballot(heavy);
@@ -167,7 +232,7 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), far_min, nimp);
+                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), far_min, outer_min, nimp);
             }
         }
     }
@@ -209,7 +274,7 @@ __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uin
         const bool move = valid && !drop && dv < c.thr;
         const bool keep = valid && !drop && !move;
         if (drop || move)
-            S.infar[v] = 0;
+            S.infar[v] &= ~1; // each vertex sits at most once in a pile
         if (move)
             S.stamp[v] = c.tag;
         if (keep)
@@ -223,6 +288,52 @@ __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uin
         k = wave_alloc(c.kept_cnt, keep);
         if (keep)
             c.far_out[k] = v;
+    }
+}
+
+// Outer pile pass, when the band threshold has passed the pile bound: entries
+// already settled are dropped, entries below the new bound join the inner
+// pile (unless already there), the rest stay in the outer pile.
+struct OuterSplitCtx {
+    const int32_t *outer_in;
+    int len;
+    int worker, nworkers;
+    uint32_t thr_old, bound;
+    int32_t *inner_q;
+    int *inner_cnt;
+    int32_t *outer_out;
+    int *kept_cnt;
+};
+
+__device__ __forceinline__ void outer_split_pass(const Slab &S, const OuterSplitCtx &c,
+                                                 uint32_t &kept_min)
+{
+    const int lane = lane_id();
+    for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
+        const int i = base + lane;
+        const bool valid = i < c.len;
+        int32_t v = 0;
+        uint32_t dv = 0;
+        int32_t f = 0;
+        if (valid) {
+            v = c.outer_in[i];
+            dv = dist_get(S, v);
+            f = S.infar[v];
+        }
+        const bool drop = valid && dv < c.thr_old;
+        const bool move = valid && !drop && dv < c.bound;
+        const bool keep = valid && !drop && !move;
+        const bool join = move && !(f & 1);
+        if (drop || move)
+            S.infar[v] = (f & ~2) | (join ? 1 : 0);
+        if (keep)
+            kept_min = dv < kept_min ? dv : kept_min;
+        int k = wave_alloc(c.inner_cnt, join);
+        if (join)
+            c.inner_q[k] = v;
+        k = wave_alloc(c.kept_cnt, keep);
+        if (keep)
+            c.outer_out[k] = v;
     }
 }
 
@@ -263,9 +374,9 @@ __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 //
 // With RECORD, the in-row positions of the tight in-arcs of v are also
 // written to preds[trow[v] ..] (the slice of v's own in-row, so no allocation
-// is needed), pcnt[v] holds their number and every recorded predecessor's
-// successor count scnt is incremented once v is final; the dependency pass
-// then walks this DAG.
+// is needed), ended by -1 when there are fewer than the in-degree, and every
+// recorded predecessor's successor count scnt is incremented once v is final;
+// the dependency pass then walks this DAG.
 template <bool PACKED, int SCOPE, bool RECORD>
 __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
@@ -287,8 +398,8 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
         if (is_src) {
             // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
             store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
-            if (RECORD)
-                S.pcnt[v] = 0;
+            if (RECORD && end > beg)
+                S.preds[beg] = -1;
         }
         const bool heavy = valid && !is_src && (end - beg) > (uint32_t)c.lane_max;
         bool pend = false;
@@ -335,7 +446,8 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                 store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                 dag += tight;
                 if (RECORD) {
-                    S.pcnt[v] = (int32_t)tight;
+                    if (beg + tight < end)
+                        S.preds[beg + tight] = -1;
                     for (uint32_t j = 0; j < tight; ++j) {
                         uint32_t u, w;
                         arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[beg + j], g.wshift,
@@ -401,8 +513,8 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
                 store_u64<SCOPE>(&S.sigma[hv], acc);
                 store_f64<SCOPE>(&S.delta[hv], RECORD ? 0.0 : -1.0);
                 dag += tight;
-                if (RECORD)
-                    S.pcnt[hv] = (int32_t)tight;
+                if (RECORD && hb + tight < he)
+                    S.preds[hb + tight] = -1;
             }
             if (RECORD && all_ready)
                 for (uint32_t j = lane; j < tight; j += WAVE) {
@@ -568,12 +680,12 @@ __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, do
         const int i = base + lane;
         const bool valid = i < c.len;
         int32_t w = 0;
-        uint32_t pb = 0, np = 0;
+        uint32_t pb = 0, pe = 0;
         double dw = 0.0, sw = 1.0;
         if (valid) {
             w = c.items[i];
             pb = g.trow[w];
-            np = (uint32_t)S.pcnt[w];
+            pe = g.trow[w + 1];
             dw = load_f64<SCOPE>(&S.delta[w]);
             sw = (double)S.sigma[w];
             if (w != c.s) {
@@ -584,12 +696,18 @@ __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, do
                     bc[o] += dw;
             }
         }
-        const bool heavy = valid && np > (uint32_t)c.lane_max;
-        if (valid && !heavy) {
-            for (uint32_t j = 0; j < np; ++j) {
-                const uint32_t pos = (uint32_t)S.preds[pb + j];
+        // A lane walks up to lane_max recorded predecessors; the rest of a
+        // longer list is finished by the whole wave.
+        bool more = false;
+        if (valid) {
+            const uint32_t lim = pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
+            uint32_t j = pb;
+            for (; j < lim; ++j) {
+                const int32_t pos = S.preds[j];
+                if (pos < 0)
+                    break;
                 uint32_t uu, wgt;
-                arc_at<PACKED>(g.tarc, g.twt, pos, g.wshift, g.wmask, uu, wgt);
+                arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, uu, wgt);
                 const int32_t u = (int32_t)uu;
                 const double term = (double)S.sigma[u] / sw * (1.0 + dw);
                 if (c.ebc) // the term is the source's dependency on the arc u -> w
@@ -599,27 +717,38 @@ __device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, do
                 if (fin)
                     c.next_q[k] = u;
             }
+            more = j == lim && lim < pe;
+            pb = lim;
         }
-        uint64_t hm = __ballot(heavy);
+        uint64_t hm = __ballot(more);
         while (hm) {
             const int l = __ffsll((unsigned long long)hm) - 1;
             hm &= hm - 1;
             const uint32_t hb = (uint32_t)__shfl((int)pb, l);
-            const uint32_t hn = (uint32_t)__shfl((int)np, l);
+            const uint32_t he = (uint32_t)__shfl((int)pe, l);
             const double hd = __shfl(dw, l);
             const double hs = __shfl(sw, l);
-            for (uint32_t j = lane; j < hn; j += WAVE) {
-                const uint32_t pos = (uint32_t)S.preds[hb + j];
-                uint32_t uu, wgt;
-                arc_at<PACKED>(g.tarc, g.twt, pos, g.wshift, g.wmask, uu, wgt);
-                const int32_t u = (int32_t)uu;
-                const double term = (double)S.sigma[u] / hs * (1.0 + hd);
-                if (c.ebc)
-                    unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
-                const bool fin = push_dependency<SCOPE>(S, u, term);
+            for (uint32_t e0 = hb; e0 < he; e0 += WAVE) {
+                const uint32_t e = e0 + lane;
+                const int32_t pos = e < he ? S.preds[e] : -1;
+                const uint64_t endm = __ballot(pos < 0);
+                const int stop = endm ? __ffsll((unsigned long long)endm) - 1 : WAVE;
+                bool fin = false;
+                int32_t u = 0;
+                if (lane < stop) {
+                    uint32_t uu, wgt;
+                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, uu, wgt);
+                    u = (int32_t)uu;
+                    const double term = (double)S.sigma[u] / hs * (1.0 + hd);
+                    if (c.ebc)
+                        unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
+                    fin = push_dependency<SCOPE>(S, u, term);
+                }
                 const int k = wave_alloc(c.next_cnt, fin);
                 if (fin)
                     c.next_q[k] = u;
+                if (endm)
+                    break;
             }
         }
     }

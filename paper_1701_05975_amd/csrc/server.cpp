@@ -178,6 +178,8 @@ class HipExec {
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.ebc = nullptr;
         a.emap = nullptr;
+        a.vw = opts_.compute.virtual_warp;
+        a.node_parallel = 0;
         a.delta = (uint32_t)delta_for(g);
         a.lane_max = lane_max_for(g);
         a.stats = &dc->stats;

@@ -30,30 +30,24 @@ struct DevGraph {
 
 // ---------------------------------------------------------------------------
 // Per-source state ("slab").  One slab per source in flight.
+//
+// Distances, the most often read field (every arc relaxation and every
+// tightness test reads one at a random vertex), stay a dense array so that
+// a cache line holds as many of them as possible.  The other per-vertex
+// fields, which the count, dependency and split passes touch together,
+// share one 32-byte record, so that such a visit of a random vertex fetches
+// one line instead of one line per field.  Record layout:
 // ---------------------------------------------------------------------------
-struct Slab {
-    uint32_t *d;       // tentative / final distance, BC_INF = unreached
-    uint64_t *sigma;   // shortest-path count (0 = not yet final in the count pass)
-    double *delta;     // dependency (negative = not yet final in the dependency pass)
-    double *bcp;       // per-slab partial centrality (batched form)
-    int32_t *stamp;    // tag of the latest near queue the vertex entered
-    int32_t *infar;    // 1 while the vertex sits in the far pile
-    int32_t *order;    // members of each band, band after band
-    int32_t *qa, *qb;  // near queues / pending lists
-    int32_t *fa, *fb;  // far piles
-    int32_t *band_off; // band b = order[band_off[b] .. band_off[b+1])
-    int64_t *hdr;      // [0] = last queue tag used by this slab
-    uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
-    int32_t H;         // number of LDS-resident distances (0 = none)
-    int32_t *scnt;     // shortest-path-DAG successors not yet accumulated (batched form)
-    int32_t *pcnt;     // number of recorded DAG predecessors of each vertex
-    int32_t *preds;    // in-row positions of v's DAG in-arcs, at preds[trow[v] ...]
-};
+#define VREC_BYTES 32
+#define VREC_STAMP 0  // i32 tag of the latest near queue the vertex entered
+#define VREC_INFAR 4  // i32 bit 0: in the inner far pile; bit 1: in the outer far pile
+#define VREC_SCNT 8   // i32 shortest-path-DAG successors not yet accumulated
+#define VREC_SIGMA 16 // u64 shortest-path count (0 = not yet final in the count pass)
+#define VREC_DELTA 24 // f64 dependency (negative = not yet final in the pull pass)
 
 // Byte offsets of the slab arrays inside one slot (all 256-byte aligned).
 struct SlabLayout {
-    size_t d, sigma, delta, bcp, stamp, infar, order, qa, qb, fa, fb, band_off, hdr, scnt, pcnt,
-        preds, stride;
+    size_t d, rec, bcp, order, qa, qb, fa, fb, oa, ob, band_off, hdr, preds, stride;
 };
 
 // ---------------------------------------------------------------------------

@@ -201,6 +201,31 @@ def rmat_graph(scale: int, n_draws: int, a: float, b: float, c: float, wlo: int,
                     meta=dict(family="rmat", seed=seed, wlo=wlo, whi=whi, draws=n_draws))
 
 
+def kronecker_graph(scale: int, edge_factor: int, wlo: int, whi: int, seed: int,
+                    a: float = 0.57, b: float = 0.19, c: float = 0.19) -> CSRGraph:
+    """Undirected Kronecker-like graph: R-MAT draws (edge_factor * 2^scale),
+    self-loops dropped, each unordered pair kept once, uniform weights."""
+    rng = np.random.default_rng(seed)
+    n = 1 << scale
+    draws = edge_factor * n
+    ta, tb, tc = np.float32(a), np.float32(a + b), np.float32(a + b + c)
+    u = np.zeros(draws, dtype=np.int64)
+    v = np.zeros(draws, dtype=np.int64)
+    for _ in range(scale):
+        x = rng.random(draws, dtype=np.float32)
+        u = (u << 1) | (x >= tb)
+        v = (v << 1) | (((x >= ta) & (x < tb)) | (x >= tc))
+    perm = rng.permutation(n).astype(np.int64)
+    u, v = perm[u], perm[v]
+    ok = u != v
+    lo, hi = np.minimum(u[ok], v[ok]), np.maximum(u[ok], v[ok])
+    key = np.unique(lo * n + hi)
+    eu, ev = key // n, key % n
+    ew = rng.integers(wlo, whi + 1, size=eu.shape[0])
+    return undirected_from_edges(n, eu, ev, ew, name=f"kron_s{scale}_ef{edge_factor}",
+                                 meta=dict(family="kronecker", seed=seed, wlo=wlo, whi=whi))
+
+
 def random_graph(n: int, p: float, wlo: int, whi: int, seed: int, directed: bool = False) -> CSRGraph:
     """Bernoulli(p) simple graph on n vertices (small parity and pin cases)."""
     rng = np.random.default_rng(seed)

@@ -35,6 +35,11 @@ OPTION_SETS = [
     dict(lds_vertices=5, wg_threads=256),
     dict(dep_mode=2),
     dict(dep_mode=2, accumulate=2, lane_max_deg=1),
+    dict(virtual_warp=1),
+    dict(virtual_warp=8, node_parallel=1),
+    dict(virtual_warp=64),
+    dict(node_parallel=1, mode=bc.BC_MODE_BATCHED, wg_threads=512),
+    dict(mode=bc.BC_MODE_PLAIN, virtual_warp=16),
 ]
 
 
