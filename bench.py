@@ -100,6 +100,8 @@ def run_ablation(args):
         out = torch.empty(g.n, dtype=torch.float64, device="cuda")
         ref = None
         for name, extra in ABLATION_VARIANTS:
+            if args.variants and not any(x in name for x in args.variants.split(",")):
+                continue
             o = bc.make_options(wg_threads=1024, stream=stream.cuda_stream, **extra)
             bc.bc_compute_device(G.handle, s_dev.data_ptr(), len(srcs), out.data_ptr(), o)
             torch.cuda.synchronize()
@@ -303,6 +305,7 @@ def main():
     ap.add_argument("--edges", action="store_true",
                     help="time node + edge betweenness (bc_compute_edges_device)")
     ap.add_argument("--ablation-sources", type=int, default=256)
+    ap.add_argument("--variants", default="", help="ablation: comma-separated name parts to run")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
     ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")

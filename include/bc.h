@@ -118,8 +118,9 @@ typedef struct {
     int32_t mode;         /* bc_mode */
     int32_t batch;        /* batched: sources in flight (state slabs); 0 = fill the GPU */
     int32_t delta;        /* near-far band width in weight units (>= 1); 0 = heuristic */
-    int32_t lane_max_deg; /* vertices with at most this many arcs are scanned by one lane,
-                             larger ones by a whole 64-lane wave */
+    int32_t lane_max_deg; /* count and dependency passes: vertices with at most this many
+                             in-arcs (recorded predecessors) are handled by one lane, larger
+                             ones by a whole 64-lane wave */
     int32_t wg_threads;   /* batched: threads per workgroup (256, 512 or 1024) */
     int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best */
     int32_t accumulate;   /* 0 = default, 1 = per-slot partial sums + reduction,
@@ -129,9 +130,10 @@ typedef struct {
     int32_t dep_mode;     /* batched dependency pass: 0 = default (1), 1 = push along the
                              shortest-path DAG recorded by the count pass (Kahn's order),
                              2 = pull over out-arcs band by band in reverse */
-    int32_t virtual_warp; /* frontier expansion: 0 = one lane per vertex up to lane_max_deg
-                             arcs, a whole wave above; 1, 2, 4, ..., 64 = a fixed group of that
-                             many lanes per vertex (the warp-centric mapping of Sec. 3.4) */
+    int32_t virtual_warp; /* frontier expansion: 0 = by degree, one lane per vertex up to 8
+                             arcs, a group of 8 lanes up to 128, a whole wave above;
+                             1, 2, 4, ..., 64 = a fixed group of that many lanes per vertex
+                             (the warp-centric mapping of Sec. 3.4) */
     int32_t node_parallel;/* batched frontier expansion: 0 = over the queue (work-efficient,
                              Sec. 3.3); 1 = over every vertex, expanding those queued
                              (node-parallel, Alg. 2) -- for comparison only */

@@ -102,6 +102,12 @@ struct ExpandCtx {
 // lane are in flight instead of one dependent chain per arc.
 #define LANE_UNROLL 4
 
+// Adaptive expansion (Sec. 3.4's degree-aware mapping, three tiers): a vertex
+// with at most EXPAND_GROUP arcs is walked by one lane, one with at most
+// EXPAND_WAVE_DEG by a group of EXPAND_GROUP lanes, a larger one by the wave.
+#define EXPAND_GROUP 8
+#define EXPAND_WAVE_DEG 128
+
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
                                       uint32_t du, uint32_t &far_min, uint32_t &outer_min,
@@ -202,8 +208,11 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
                 dv = dist_get(S, v);
             }
         }
-        const bool heavy = valid && (end - beg) > (uint32_t)c.lane_max;
-        if (valid && !heavy) {
+        const uint32_t deg = end - beg;
+        const bool light = valid && deg <= (uint32_t)EXPAND_GROUP;
+        const bool mid = valid && deg > (uint32_t)EXPAND_GROUP && deg <= (uint32_t)EXPAND_WAVE_DEG;
+        const bool heavy = valid && deg > (uint32_t)EXPAND_WAVE_DEG;
+        if (light) {
             for (uint32_t e0 = beg; e0 < end; e0 += LANE_UNROLL) {
                 uint32_t u[LANE_UNROLL], w[LANE_UNROLL], du[LANE_UNROLL];
 #pragma unroll
@@ -220,6 +229,42 @@ __device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c
                 for (int j = 0; j < LANE_UNROLL; ++j)
                     if (e0 + j < end)
                         relax<SCOPE>(S, c, u[j], dv + w[j], du[j], far_min, outer_min, nimp);
+            }
+        }
+        // Medium degree: up to WAVE / EXPAND_GROUP vertices at a time, one per
+        // group of lanes.  The shuffles run on every lane: a lane whose group
+        // has no vertex may be the source another group reads from.
+        uint64_t mm = __ballot(mid);
+        const int grp = lane / EXPAND_GROUP, sub = lane % EXPAND_GROUP;
+        while (mm) {
+            uint64_t t = mm;
+            for (int k = 0; k < grp; ++k)
+                t &= t - 1;
+            const bool have = t != 0;
+            const int l = have ? __ffsll((unsigned long long)t) - 1 : 0;
+            for (int k = 0; k < WAVE / EXPAND_GROUP; ++k)
+                mm &= mm - 1;
+            const uint32_t mb = (uint32_t)__shfl((int)beg, l);
+            const uint32_t me0 = (uint32_t)__shfl((int)end, l);
+            const uint32_t md = (uint32_t)__shfl((int)dv, l);
+            const uint32_t me = have ? me0 : mb;
+            constexpr int G = EXPAND_GROUP;
+            for (uint32_t e0 = mb + sub; e0 < me; e0 += G * 2) {
+                uint32_t u[2], w[2], du[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    u[j] = 0;
+                    w[j] = 0;
+                    if (e0 + G * j < me)
+                        arc_at<PACKED>(g.arc, g.wt, e0 + G * j, g.wshift, g.wmask, u[j], w[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    du[j] = e0 + G * j < me ? dist_get(S, u[j]) : 0u;
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (e0 + G * j < me)
+                        relax<SCOPE>(S, c, u[j], md + w[j], du[j], far_min, outer_min, nimp);
             }
         }
         uint64_t hm = __ballot(heavy);
