@@ -446,9 +446,11 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             if (RECORD && end > beg)
                 S.preds[beg] = -1;
         }
-        const bool heavy = valid && !is_src && (end - beg) > (uint32_t)c.lane_max;
+        const uint32_t deg = end - beg;
+        const bool heavy = valid && !is_src && deg > (uint32_t)EXPAND_WAVE_DEG;
+        const bool mid = valid && !is_src && !heavy && deg > (uint32_t)c.lane_max;
         bool pend = false;
-        if (valid && !is_src && !heavy) {
+        if (valid && !is_src && !heavy && !mid) {
             const uint32_t dv = dist_get(S, v);
             uint64_t acc = 0;
             bool ready = true, ovf = false;
@@ -507,6 +509,87 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
             const int k = wave_alloc(c.pend_cnt, pend);
             if (pend)
                 c.pend_q[k] = v;
+        }
+        // Medium in-degree: a group of EXPAND_GROUP lanes per vertex, up to
+        // WAVE / EXPAND_GROUP vertices at a time.  Shuffles and ballots run on
+        // every lane; each group reads only its own bits.
+        uint64_t mm = __ballot(mid);
+        const int grp = lane / EXPAND_GROUP, sub = lane % EXPAND_GROUP;
+        const int gshift = grp * EXPAND_GROUP;
+        const uint64_t gbits = (1ull << EXPAND_GROUP) - 1;
+        while (mm) {
+            uint64_t t = mm;
+            for (int k = 0; k < grp; ++k)
+                t &= t - 1;
+            const bool have = t != 0;
+            const int l = have ? __ffsll((unsigned long long)t) - 1 : 0;
+            for (int k = 0; k < WAVE / EXPAND_GROUP; ++k)
+                mm &= mm - 1;
+            const int32_t mv = __shfl(v, l);
+            const uint32_t mb = (uint32_t)__shfl((int)beg, l);
+            const uint32_t me0 = (uint32_t)__shfl((int)end, l);
+            const uint32_t me = have ? me0 : mb;
+            const uint32_t mdv = have ? dist_get(S, mv) : 0u;
+            uint64_t acc = 0;
+            bool ready = true, ovf = false;
+            uint32_t rec = 0; // tight arcs of the group so far (uniform in the group)
+            for (uint32_t e0 = mb; e0 < me; e0 += EXPAND_GROUP) {
+                const uint32_t e = e0 + sub;
+                bool tt = false;
+                if (e < me) {
+                    uint32_t u, w;
+                    arc_at<PACKED>(g.tarc, g.twt, e, g.wshift, g.wmask, u, w);
+                    if (dist_get(S, u) + w == mdv) {
+                        const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                        if (su == 0) {
+                            ready = false;
+                        } else {
+                            const uint64_t x = acc + su;
+                            ovf |= x < acc;
+                            acc = x;
+                            tt = true;
+                        }
+                    }
+                }
+                const uint64_t gm = (__ballot(tt) >> gshift) & gbits;
+                if (RECORD && tt)
+                    S.preds[mb + rec + __popcll(gm & ((1ull << sub) - 1))] = (int32_t)e;
+                rec += (uint32_t)__popcll(gm);
+                if ((__ballot(!ready) >> gshift) & gbits)
+                    break;
+            }
+            bool gready = ready;
+            for (int o = 1; o < EXPAND_GROUP; o <<= 1) {
+                const uint64_t y = __shfl_xor(acc, o);
+                const int oy = __shfl_xor((int)ovf, o);
+                const int ry = __shfl_xor((int)gready, o);
+                const uint64_t z = acc + y;
+                ovf = ovf || oy || z < acc;
+                acc = z;
+                gready = gready && ry;
+            }
+            if (have && gready && sub == 0) {
+                if (ovf) {
+                    report_sigma_overflow(c);
+                    acc = ~0ull;
+                }
+                store_u64<SCOPE>(&S.sigma[mv], acc);
+                store_f64<SCOPE>(&S.delta[mv], RECORD ? 0.0 : -1.0);
+                dag += rec;
+                if (RECORD && mb + rec < me)
+                    S.preds[mb + rec] = -1;
+            }
+            if (RECORD && have && gready)
+                for (uint32_t j = sub; j < rec; j += EXPAND_GROUP) {
+                    uint32_t u, w;
+                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[mb + j], g.wshift, g.wmask,
+                                   u, w);
+                    __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+                }
+            const bool p = have && !gready && sub == 0;
+            const int k = wave_alloc(c.pend_cnt, p);
+            if (p)
+                c.pend_q[k] = mv;
         }
         uint64_t hm = __ballot(heavy);
         while (hm) {
