@@ -302,6 +302,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--dep-mode", type=int, default=0)
+    ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (16, 32)")
     ap.add_argument("--edges", action="store_true",
                     help="time node + edge betweenness (bc_compute_edges_device)")
     ap.add_argument("--ablation-sources", type=int, default=256)
@@ -357,6 +358,7 @@ def main():
                     wg_threads=args.wg or pinned.get("wg_threads", 0),
                     lane_max_deg=args.lane_max or pinned.get("lane_max_deg", 0),
                     dep_mode=args.dep_mode or pinned.get("dep_mode", 0),
+                    lds_bits=args.lds_bits or pinned.get("lds_bits", 0),
                     batch=args.batch, accumulate=args.accumulate,
                     stream=stream.cuda_stream)
         base.update(kw)
@@ -433,6 +435,7 @@ def main():
             "delta": last.delta, "wg_threads": last.wg_threads, "lane_max_deg": last.lane_max_deg,
             "batch": last.batch, "accumulate": last.accumulate, "dep_mode": last.dep_mode,
             "lds_vertices": last.lds_vertices,
+            "lds_bits": last.lds_bits,
             "reached": last.reached, "arcs_out_reached": last.arcs_out_reached,
             "dag_arcs": last.dag_arcs, "improvements": last.improvements,
             "bands": last.bands, "iterations": last.iterations,

@@ -137,6 +137,10 @@ typedef struct {
     int32_t node_parallel;/* batched frontier expansion: 0 = over the queue (work-efficient,
                              Sec. 3.3); 1 = over every vertex, expanding those queued
                              (node-parallel, Alg. 2) -- for comparison only */
+    int32_t lds_bits;     /* batched: width of the LDS distance entries: 0 = auto (16 for
+                             graphs renumbered by in-degree, else 32), 16 or 32.  With 16 the
+                             cache holds twice the vertices; distances of 65535 and more of
+                             those vertices are kept in device memory instead */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -159,7 +163,7 @@ typedef struct {
                                  in initialisation, frontier expansion, count rounds,
                                  dependency rounds and far-pile splits */
     int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode,
-        virtual_warp, node_parallel;
+        virtual_warp, node_parallel, lds_bits;
 } bc_stats;
 
 /*

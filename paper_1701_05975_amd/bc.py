@@ -54,7 +54,7 @@ class bc_options(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("accumulate", ctypes.c_int32),
                 ("lds_vertices", ctypes.c_int32), ("dep_mode", ctypes.c_int32),
                 ("virtual_warp", ctypes.c_int32), ("node_parallel", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("lds_bits", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class bc_stats(ctypes.Structure):
@@ -70,7 +70,7 @@ class bc_stats(ctypes.Structure):
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
                 ("dep_mode", ctypes.c_int32), ("virtual_warp", ctypes.c_int32),
-                ("node_parallel", ctypes.c_int32)]
+                ("node_parallel", ctypes.c_int32), ("lds_bits", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -166,6 +166,7 @@ def _ptr(a: np.ndarray):
 
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
                  accumulate=0, lds_vertices=0, dep_mode=0, virtual_warp=0, node_parallel=0,
+                 lds_bits=0,
                  stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
@@ -174,6 +175,7 @@ def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotun
     o.dep_mode = dep_mode
     o.virtual_warp = virtual_warp
     o.node_parallel = node_parallel
+    o.lds_bits = lds_bits
     o.stream = stream
     return o
 

@@ -75,7 +75,7 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
                 ResolvedOptions t = c;
                 t.wg_threads = nt;
                 int H = 0, per_cu = 1;
-                batched_lds_plan(g, nt, t.accumulate == 2, o.lds_vertices, H, per_cu);
+                batched_lds_plan(g, nt, t.accumulate == 2, o.lds_vertices, t.lds_bits, H, per_cu);
                 t.lds_vertices = H;
                 t.batch = std::max(1, (int)std::min<int64_t>((int64_t)g->num_cus * per_cu,
                                                              sample));
@@ -122,7 +122,8 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
     if (!o.wg_threads && r.wg_threads != g->tuned.wg_threads) {
         r.wg_threads = g->tuned.wg_threads;
         int H = 0, per_cu = 1;
-        batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, H, per_cu);
+        batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_bits, H,
+                         per_cu);
         r.lds_vertices = H;
         if (!o.batch)
             r.batch = std::max(1, (int)std::min<int64_t>((int64_t)g->num_cus * per_cu, k));

@@ -516,29 +516,43 @@ int default_delta(const bc_graph *g)
     return (int)d;
 }
 
-int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc)
+
+int lds_bits_for(const bc_graph *g, int requested)
 {
-    return batched_blocks_per_cu(g->packed, nt, atomic_bc);
+    if (requested == 16 || requested == 32)
+        return requested;
+    // Graphs renumbered for skewed in-degrees are small-world: their distances
+    // stay small, so 16-bit entries rarely overflow to device memory.
+    return g->renumbered ? 16 : 32;
 }
 
-void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int &H,
-                      int &per_cu)
+static size_t lds_bytes_for(int H, int bits)
+{
+    return bits == 16 ? (size_t)((H + 1) / 2) * 4 : (size_t)H * 4;
+}
+
+void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
+                      int &H, int &per_cu)
 {
     // Workgroups per CU are set by registers; the LDS (160 KB per CU) is then
     // split among them for the per-source distance caches.
-    const int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc);
+    const bool w16 = bits == 16;
+    const int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc, w16);
     const size_t lds_cu = 160 * 1024, reserve = 2 * 1024;
-    int cap = (int)((lds_cu / (size_t)std::max(occ, 1) - reserve) / sizeof(uint32_t));
+    int cap = (int)((lds_cu / (size_t)std::max(occ, 1) - reserve) / (size_t)(bits / 8));
+    cap &= ~1;
     if (requested < 0)
         H = 0;
     else if (requested > 0)
         H = std::min(requested, g->n);
     else
         H = std::min(cap, g->n);
-    per_cu = H > 0 ? batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, (size_t)H * 4) : occ;
+    per_cu = H > 0 ? batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, w16,
+                                               lds_bytes_for(H, bits))
+                   : occ;
     if (per_cu < 1) {
         H = std::min(cap, g->n);
-        per_cu = batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, (size_t)H * 4);
+        per_cu = batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, w16, lds_bytes_for(H, bits));
     }
     per_cu = std::max(per_cu, 1);
 }
@@ -561,6 +575,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "unknown dependency mode %d", o.dep_mode);
     if (o.virtual_warp < 0 || o.virtual_warp > 64 || (o.virtual_warp & (o.virtual_warp - 1)))
         throw bc_error(BC_E_INVAL, "virtual_warp must be 0 or a power of two up to 64");
+    if (o.lds_bits != 0 && o.lds_bits != 16 && o.lds_bits != 32)
+        throw bc_error(BC_E_INVAL, "lds_bits must be 0, 16 or 32");
     if (o.node_parallel < 0 || o.node_parallel > 1)
         throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
     r.mode = o.mode == BC_MODE_PLAIN ? BC_MODE_PLAIN : BC_MODE_BATCHED;
@@ -575,7 +591,9 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.vw = o.virtual_warp;
     r.node_parallel = o.node_parallel;
     int per_cu = 1;
-    batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_vertices, per_cu);
+    r.lds_bits = lds_bits_for(g, o.lds_bits);
+    batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_bits,
+                     r.lds_vertices, per_cu);
     const int fill = g->num_cus * per_cu;
     int64_t b = o.batch ? o.batch : fill;
     b = std::min<int64_t>(b, std::max<int64_t>(k, 1));
@@ -646,6 +664,7 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->wg_threads = r.wg_threads;
     st->accumulate = r.accumulate;
     st->lds_vertices = r.lds_vertices;
+    st->lds_bits = r.lds_bits;
     st->dep_mode = r.dep_mode;
     st->virtual_warp = r.vw;
     st->node_parallel = r.node_parallel;
@@ -694,6 +713,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.iperm = g->iperm_dev();
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
+        a.lds16 = r.lds_bits == 16;
         a.kahn = r.dep_mode == 1 ? 1 : 0;
         a.vw = r.vw;
         a.node_parallel = r.node_parallel;

@@ -51,6 +51,7 @@ struct ResolvedOptions {
     int accumulate = 1;
     int autotune = 0;
     int lds_vertices = 0; // H: distances kept in LDS per source
+    int lds_bits = 32;    // width of an LDS distance entry (16 or 32)
     int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
     int vw = 0;           // expansion lanes per vertex (0 adaptive)
     int node_parallel = 0;
@@ -120,10 +121,11 @@ struct bc_result {
 
 SlabLayout slab_layout(int32_t n, int64_t pred_slots);
 int default_delta(const bc_graph *g);
-int batched_occupancy(const bc_graph *g, int nt, bool atomic_bc);
+// Width of the LDS distance entries for a requested width (0 = by graph).
+int lds_bits_for(const bc_graph *g, int requested);
 // LDS-resident distances per source and the matching workgroups per CU.
-void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int &H,
-                      int &per_cu);
+void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
+                      int &H, int &per_cu);
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
                     const bc_options *opt, double *bc_dev, bc_stats *stats,

@@ -48,6 +48,7 @@ struct Slab {
     int64_t *hdr;      // [0] = last queue tag used by this slab
     uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
     int32_t H;         // number of LDS-resident distances (0 = none)
+    int32_t w16;       // LDS entries are 16-bit; LDS16_FAR = look in d[]
     int32_t *preds;    // in-row positions of v's DAG in-arcs, at preds[trow[v] ...],
                        // ended by -1 when fewer than the in-degree
 };
@@ -70,6 +71,7 @@ __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slo
     s.hdr = (int64_t *)(p + L.hdr);
     s.ld = nullptr;
     s.H = 0;
+    s.w16 = 0;
     s.preds = (int32_t *)(p + L.preds);
     return s;
 }
@@ -81,22 +83,49 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 __device__ __forceinline__ lds_u32 *lds_ptr(uint32_t *p) { return (lds_u32 *)p; }
 
+// With 16-bit entries LDS16_INF marks an unreached resident vertex, and a
+// resident vertex whose distance does not fit below LDS16_FAR holds
+// LDS16_FAR in LDS and its distance in d[]; d[] of a resident vertex only
+// ever holds such values (or BC_INF).
+#define LDS16_INF 0xffffu
+#define LDS16_FAR 0xfffeu
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+
+__device__ __forceinline__ lds_u16 *lds16_ptr(uint32_t *p) { return (lds_u16 *)p; }
+
 __device__ __forceinline__ uint32_t dist_get(const Slab &S, uint32_t u)
 {
     uint32_t r;
-    if ((int32_t)u < S.H)
-        r = lds_ptr(S.ld)[u];
-    else
+    if ((int32_t)u < S.H) {
+        if (S.w16) {
+            r = lds16_ptr(S.ld)[u];
+            if (r == LDS16_INF)
+                r = BC_INF;
+            else if (r == LDS16_FAR)
+                r = S.d[u];
+        } else {
+            r = lds_ptr(S.ld)[u];
+        }
+    } else {
         r = S.d[u];
+    }
     return r;
 }
 
 __device__ __forceinline__ void dist_set(const Slab &S, uint32_t u, uint32_t v)
 {
-    if ((int32_t)u < S.H)
-        lds_ptr(S.ld)[u] = v;
-    else
+    if ((int32_t)u < S.H) {
+        if (S.w16) {
+            lds16_ptr(S.ld)[u] =
+                (uint16_t)(v < LDS16_FAR ? v : v == BC_INF ? LDS16_INF : LDS16_FAR);
+            if (v >= LDS16_FAR)
+                S.d[u] = v;
+        } else {
+            lds_ptr(S.ld)[u] = v;
+        }
+    } else {
         S.d[u] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------

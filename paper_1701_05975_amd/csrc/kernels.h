@@ -20,6 +20,7 @@ struct BatchArgs {
     const int32_t *iperm;         // caller id -> internal id (null: identity)
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
+    int32_t lds16;                // LDS entries are 16-bit (65535 = kept in the slab)
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
     int32_t vw;                   // expansion: 0 adaptive lane/wave, else lanes per vertex
     int32_t node_parallel;        // expansion scans every vertex instead of the queue
@@ -63,8 +64,8 @@ struct PlainArgs {
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st);
-int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, size_t lds_bytes);
-int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc);
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, bool w16, size_t lds_bytes);
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, bool w16);
 hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
                                   double *out, const int32_t *perm, hipStream_t st);
 hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,

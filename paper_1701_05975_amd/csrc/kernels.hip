@@ -58,7 +58,7 @@ __device__ __forceinline__ void phase_mark(WgCtl &C, long long &t0, int phase)
 // Runs the count (or dependency) rounds over the members order[b0, b1) of
 // one band inside a workgroup.  Returns false if the round bound tripped.
 template <bool PACKED, int NT, bool SIGMA, bool ATOMIC_BC, bool RECORD>
-__device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const BatchArgs &a,
+__device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const BatchArgs &a,
                                int32_t s, long long idx, int b0, int b1, double *bc,
                                uint64_t &st_arcs, uint64_t &st_dag)
 {
@@ -108,7 +108,7 @@ __device__ bool wg_band_rounds(const DevGraph &g, const Slab &S, WgCtl &C, const
     }
 }
 
-template <bool PACKED, int NT, bool ATOMIC_BC>
+template <bool PACKED, int NT, bool ATOMIC_BC, bool W16>
 __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 {
     __shared__ WgCtl C;
@@ -120,6 +120,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
     Slab S = slab_at(a.slab_base, a.L, blockIdx.x);
     S.ld = lds_dist;
     S.H = a.H;
+    S.w16 = W16; // a compile-time constant: each instantiation keeps one distance path
     if (!ATOMIC_BC)
         for (int v = tid; v < n; v += NT)
             S.bcp[v] = 0.0;
@@ -162,10 +163,17 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.gen = 0;
         }
         // Initialisation (Alg. 1): d = inf and sigma = 0 everywhere.
-        for (int v = tid; v < S.H; v += NT)
-            S.ld[v] = BC_INF;
-        for (int v = S.H + tid; v < n; v += NT)
-            S.d[v] = BC_INF;
+        if (S.w16) {
+            for (int v = tid; v < (S.H + 1) / 2; v += NT)
+                lds_ptr(S.ld)[v] = 0xffffffffu; // both entries LDS16_INF
+            for (int v = tid; v < n; v += NT)
+                S.d[v] = BC_INF;
+        } else {
+            for (int v = tid; v < S.H; v += NT)
+                S.ld[v] = BC_INF;
+            for (int v = S.H + tid; v < n; v += NT)
+                S.d[v] = BC_INF;
+        }
         for (int v = tid; v < n; v += NT)
             S.sigma[v] = 0;
         if (a.kahn)
@@ -415,8 +423,16 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         phase_mark(C, tmark, 3);
         // The LDS-resident distances go back to the slab so that the slab
         // holds the complete per-source state.
-        for (int v = tid; v < S.H; v += NT)
-            S.d[v] = S.ld[v];
+        if (S.w16) {
+            for (int v = tid; v < S.H; v += NT) {
+                const uint32_t x = lds16_ptr(S.ld)[v];
+                if (x < LDS16_FAR)
+                    S.d[v] = x; // else d[v] already holds it (or BC_INF)
+            }
+        } else {
+            for (int v = tid; v < S.H; v += NT)
+                S.d[v] = S.ld[v];
+        }
         __syncthreads();
         if (C.abort) {
             // Leave the slab reusable and report; the result is not valid.
@@ -843,70 +859,61 @@ __global__ void k_graph_vertex_info(DevGraph g, int32_t *dnode, int32_t *deg)
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <bool PACKED, int NT, bool ATOMIC>
+template <bool PACKED, int NT, bool ATOMIC, bool W16>
 static void launch_batched_t(const BatchArgs &a, int nslabs, hipStream_t st)
 {
-    const size_t lds = (size_t)a.H * sizeof(uint32_t);
+    const size_t lds = W16 ? (size_t)((a.H + 1) / 2) * 4 : (size_t)a.H * sizeof(uint32_t);
     if (lds > 48 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC>,
+        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC, W16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC>), dim3(nslabs), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC, W16>), dim3(nslabs), dim3(NT), lds, st, a);
 }
+
+// Every instantiation of the batched kernel: (packed arcs, threads, atomic
+// output, 16-bit LDS distances).
+#define BC_FOR_EACH_BATCHED(X)                                                                  \
+    X(true, 256, false, false) X(true, 256, true, false) X(true, 512, false, false)            \
+    X(true, 512, true, false) X(true, 1024, false, false) X(true, 1024, true, false)           \
+    X(false, 256, false, false) X(false, 256, true, false) X(false, 512, false, false)         \
+    X(false, 512, true, false) X(false, 1024, false, false) X(false, 1024, true, false)        \
+    X(true, 256, false, true) X(true, 256, true, true) X(true, 512, false, true)               \
+    X(true, 512, true, true) X(true, 1024, false, true) X(true, 1024, true, true)              \
+    X(false, 256, false, true) X(false, 256, true, true) X(false, 512, false, true)            \
+    X(false, 512, true, true) X(false, 1024, false, true) X(false, 1024, true, true)
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st)
 {
-#define BC_CASE(P, T, A)                                                                        \
-    if (packed == P && nt == T && atomic_bc == A) {                                             \
-        launch_batched_t<P, T, A>(a, nslabs, st);                                               \
+    const bool w16 = a.lds16 != 0;
+#define BC_CASE(P, T, A, W)                                                                     \
+    if (packed == P && nt == T && atomic_bc == A && w16 == W) {                                 \
+        launch_batched_t<P, T, A, W>(a, nslabs, st);                                            \
         return hipGetLastError();                                                               \
     }
-    BC_CASE(true, 256, false)
-    BC_CASE(true, 256, true)
-    BC_CASE(true, 512, false)
-    BC_CASE(true, 512, true)
-    BC_CASE(true, 1024, false)
-    BC_CASE(true, 1024, true)
-    BC_CASE(false, 256, false)
-    BC_CASE(false, 256, true)
-    BC_CASE(false, 512, false)
-    BC_CASE(false, 512, true)
-    BC_CASE(false, 1024, false)
-    BC_CASE(false, 1024, true)
+    BC_FOR_EACH_BATCHED(BC_CASE)
 #undef BC_CASE
     return hipErrorInvalidValue;
 }
 
-int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc)
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, bool w16)
 {
-    return batched_blocks_per_cu_lds(packed, nt, atomic_bc, 0);
+    return batched_blocks_per_cu_lds(packed, nt, atomic_bc, w16, 0);
 }
 
-int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, size_t lds_bytes)
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, bool w16, size_t lds_bytes)
 {
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
-#define BC_OCC(P, T, A)                                                                         \
-    if (packed == P && nt == T && atomic_bc == A) {                                             \
+#define BC_OCC(P, T, A, W)                                                                      \
+    if (packed == P && nt == T && atomic_bc == A && w16 == W) {                                 \
         if (lds_bytes > 48 * 1024)                                                              \
-            (void)hipFuncSetAttribute((const void *)k_batched<P, T, A>,                         \
+            (void)hipFuncSetAttribute((const void *)k_batched<P, T, A, W>,                      \
                                       hipFuncAttributeMaxDynamicSharedMemorySize,               \
                                       (int)lds_bytes);                                          \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A>, T,        \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A, W>, T,     \
                                                          lds_bytes);                            \
     }
-    BC_OCC(true, 256, false)
-    BC_OCC(true, 256, true)
-    BC_OCC(true, 512, false)
-    BC_OCC(true, 512, true)
-    BC_OCC(true, 1024, false)
-    BC_OCC(true, 1024, true)
-    BC_OCC(false, 256, false)
-    BC_OCC(false, 256, true)
-    BC_OCC(false, 512, false)
-    BC_OCC(false, 512, true)
-    BC_OCC(false, 1024, false)
-    BC_OCC(false, 1024, true)
+    BC_FOR_EACH_BATCHED(BC_OCC)
 #undef BC_OCC
     if (e != hipSuccess || blocks < 1) {
         (void)hipGetLastError();

@@ -21,9 +21,38 @@ __device__ __forceinline__ uint32_t atomic_min_u32(uint32_t *p, uint32_t v)
 template <int SCOPE>
 __device__ __forceinline__ uint32_t dist_min(const Slab &S, uint32_t u, uint32_t v)
 {
-    if ((int32_t)u < S.H)
-        return __hip_atomic_fetch_min(lds_ptr(S.ld) + u, v, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    if ((int32_t)u < S.H) {
+        if (!S.w16)
+            return __hip_atomic_fetch_min(lds_ptr(S.ld) + u, v, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+        // 16-bit entry: LDS has no 16-bit minimum, so compare-and-swap the
+        // 32-bit word holding it.  Entries only move down (unreached, then
+        // kept in d[], then a value below LDS16_FAR, then smaller values), and
+        // each failed swap saw another lane move one of the word's two
+        // entries, so the loop ends.
+        lds_u32 *wp = lds_ptr(S.ld) + (u >> 1);
+        const uint32_t sh = (u & 1u) * 16u;
+        uint32_t cur = *wp;
+        for (;;) {
+            const uint32_t h = (cur >> sh) & 0xffffu;
+            if (h < LDS16_FAR && h <= v)
+                return h; // already at most v
+            if (v >= LDS16_FAR && h == LDS16_FAR) // kept in d[]
+                return atomic_min_u32<SCOPE>(&S.d[u], v);
+            // h is unreached, or kept in d[] while v fits, or a larger value
+            const uint32_t e = v < LDS16_FAR ? v : LDS16_FAR;
+            const uint32_t nw = (cur & ~(0xffffu << sh)) | (e << sh);
+            uint32_t expect = cur;
+            if (__hip_atomic_compare_exchange_strong(wp, &expect, nw, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                if (e == LDS16_FAR) // first value that does not fit (h was unreached)
+                    return atomic_min_u32<SCOPE>(&S.d[u], v);
+                return h < LDS16_FAR ? h : BC_INF; // d[u] held at least LDS16_FAR
+            }
+            cur = expect;
+        }
+    }
     return atomic_min_u32<SCOPE>(&S.d[u], v);
 }
 
@@ -154,7 +183,7 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
 // Fixed virtual-warp mapping (Sec. 3.4): a group of vw lanes per vertex,
 // striding over its arcs; vw = 1 is one thread per vertex, vw = 64 one wave.
 template <bool PACKED, int SCOPE>
-__device__ void expand_pass_vw(const DevGraph &g, const Slab &S, const ExpandCtx &c,
+__device__ __forceinline__ void expand_pass_vw(const DevGraph &g, const Slab &S, const ExpandCtx &c,
                                uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
 {
     const int W = c.vw;
@@ -185,7 +214,7 @@ __device__ void expand_pass_vw(const DevGraph &g, const Slab &S, const ExpandCtx
 }
 
 template <bool PACKED, int SCOPE>
-__device__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c,
+__device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c,
                             uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
 {
     if (c.vw > 0) {
@@ -423,7 +452,7 @@ __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 // recorded predecessor's successor count scnt is incremented once v is final;
 // the dependency pass then walks this DAG.
 template <bool PACKED, int SCOPE, bool RECORD>
-__device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
+__device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
 {
     const int lane = lane_id();
@@ -666,7 +695,7 @@ __device__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c,
 // caller owns it for this source (ATOMIC_BC false), with an FP64 atomic add
 // otherwise.
 template <bool PACKED, int SCOPE, bool ATOMIC_BC>
-__device__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c, double *bc)
+__device__ __forceinline__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c, double *bc)
 {
 #pragma clang fp contract(off)
     const int lane = lane_id();
@@ -800,7 +829,7 @@ __device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double
 }
 
 template <bool PACKED, int SCOPE, bool ATOMIC_BC>
-__device__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, double *bc)
+__device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, double *bc)
 {
 #pragma clang fp contract(off)
     const int lane = lane_id();

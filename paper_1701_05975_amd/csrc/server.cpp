@@ -49,6 +49,7 @@ struct SweepCtx {
     int cap = 0;
     int slots = 0;
     int lds_vertices = 0;
+    int lds16 = 0;
     std::vector<bcserve::SweepItem> items;
     ~SweepCtx()
     {
@@ -175,6 +176,7 @@ class HipExec {
         a.iperm = g->iperm_dev();
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
+        a.lds16 = c->lds16;
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.ebc = nullptr;
         a.emap = nullptr;
@@ -287,7 +289,8 @@ class HipExec {
         bc_graph *g = e.g;
         const int nt = wg_for(g);
         int H = 0, per_cu = 1;
-        batched_lds_plan(g, nt, true, opts_.compute.lds_vertices, H, per_cu);
+        const int bits = lds_bits_for(g, opts_.compute.lds_bits);
+        batched_lds_plan(g, nt, true, opts_.compute.lds_vertices, bits, H, per_cu);
         const int fill = g->num_cus * per_cu;
         const SlabLayout L = slab_layout(g->n, g->nnz);
         // A sweep takes a quarter of the GPU by default, so sweeps of other
@@ -303,6 +306,7 @@ class HipExec {
             c->slots = slots;
             c->cap = cap;
             c->lds_vertices = H;
+            c->lds16 = bits == 16;
             hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
             hip_check(hipEventCreateWithFlags(&c->done, hipEventDisableTiming), "event");
             c->ws.L = L;

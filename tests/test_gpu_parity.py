@@ -40,6 +40,9 @@ OPTION_SETS = [
     dict(virtual_warp=64),
     dict(node_parallel=1, mode=bc.BC_MODE_BATCHED, wg_threads=512),
     dict(mode=bc.BC_MODE_PLAIN, virtual_warp=16),
+    dict(lds_bits=16),
+    dict(lds_bits=32),
+    dict(lds_bits=16, lds_vertices=5, wg_threads=512),
 ]
 
 
@@ -82,6 +85,10 @@ def small_graphs():
     # skewed graphs: renumbered by in-degree on the device
     out.append(gg.ba_graph(700, 3, 1, 20, seed=9))
     out.append(gg.rmat_graph(10, 8 << 10, .57, .19, .19, 1, 9, seed=10))
+    # heavy weights: most distances exceed 16 bits (16-bit LDS entries overflow
+    # to device memory), one of them skewed so that 16-bit entries are the default
+    out.append(gg.random_graph(300, 0.02, 20000, 60000, seed=11, directed=False))
+    out.append(gg.ba_graph(700, 3, 1, 30000, seed=13))
     return out
 
 
@@ -241,6 +248,10 @@ def test_empty_and_degenerate_inputs():
     with pytest.raises(bc.BCError) as ei:
         G.bc(np.array([1], np.int32))
     assert ei.value.status == bc.BC_E_INVAL
+    for bad in (dict(lds_bits=8), dict(virtual_warp=3), dict(node_parallel=2)):
+        with pytest.raises(bc.BCError) as ei:
+            G.bc(None, **bad)
+        assert ei.value.status == bc.BC_E_INVAL, bad
 
 
 def test_directed_sinks_and_parallel_arcs():
