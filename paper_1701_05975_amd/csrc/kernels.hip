@@ -37,6 +37,7 @@ struct WgCtl {
     uint32_t thr, thr_old, far_min, bound, outer_min;
     int band_start, nbands;
     int abort;
+    int32_t prev_s; // this slab's previous source whose dependencies are not in bcp yet
     long long src_idx;
     unsigned long long iters;
     unsigned int bands, srounds, drounds;
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
     uint64_t st_arcs = 0, st_dag = 0, st_imp = 0;
     if (tid == 0) {
         C.gen = (int32_t)S.hdr[0];
+        C.prev_s = -1;
         C.iters = 0;
         C.bands = C.srounds = C.drounds = 0;
         for (int i = 0; i < 5; ++i)
@@ -152,7 +154,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             continue;
         }
         const int32_t s = a.iperm ? a.iperm[s_in] : s_in;
-        double *bc = ATOMIC_BC ? (a.item_out ? a.item_out[idx] : a.bc_out) : S.bcp;
+        // With per-slab partial sums the dependencies are added to bcp while
+        // the next source's initialisation streams over the vertices (below),
+        // instead of one random access per vertex in the dependency pass.
+        double *bc = ATOMIC_BC ? (a.item_out ? a.item_out[idx] : a.bc_out) : nullptr;
 
         // Queue tags only grow; restart them long before they could wrap.
         if (C.gen > (1 << 30)) {
@@ -166,19 +171,28 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         if (S.w16) {
             for (int v = tid; v < (S.H + 1) / 2; v += NT)
                 lds_ptr(S.ld)[v] = 0xffffffffu; // both entries LDS16_INF
-            for (int v = tid; v < n; v += NT)
-                S.d[v] = BC_INF;
         } else {
             for (int v = tid; v < S.H; v += NT)
                 S.ld[v] = BC_INF;
-            for (int v = S.H + tid; v < n; v += NT)
-                S.d[v] = BC_INF;
         }
-        for (int v = tid; v < n; v += NT)
-            S.sigma[v] = 0;
-        if (a.kahn)
-            for (int v = tid; v < n; v += NT)
-                S.scnt[v] = 0;
+        {
+            // d[] of this slab is complete here (the previous source wrote its
+            // LDS part back), so the previous source's reached vertices are
+            // those with a finite distance.
+            const int32_t ps = C.prev_s;
+            for (int v = tid; v < n; v += NT) {
+                if (!ATOMIC_BC && ps >= 0) {
+                    const uint32_t dv = S.d[v];
+                    if (dv != BC_INF && v != ps)
+                        S.bcp[v] += S.delta[v];
+                }
+                if (W16 || v >= S.H)
+                    S.d[v] = BC_INF;
+                S.sigma[v] = 0;
+                if (a.kahn)
+                    S.scnt[v] = 0;
+            }
+        }
         __syncthreads();
         if (tid == 0) {
             dist_set(S, s, 0);
@@ -445,8 +459,16 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             atomicAdd(&a.stats->reached, (unsigned long long)C.order_cnt);
             atomicAdd(&a.stats->bands, (unsigned long long)C.nbands);
             atomicAdd(&a.stats->iterations, C.iters);
+            C.prev_s = C.abort ? -1 : s;
         }
         __syncthreads();
+    }
+    // the last source's dependencies
+    if (!ATOMIC_BC && C.prev_s >= 0) {
+        const int32_t ps = C.prev_s;
+        for (int v = tid; v < n; v += NT)
+            if (S.d[v] != BC_INF && v != ps)
+                S.bcp[v] += S.delta[v];
     }
 
     // Flush per-lane statistics: one atomic per wave.

@@ -693,7 +693,8 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
 // every such u lies in this band or a later one.  A vertex other than the
 // source adds its dependency to the centrality: plainly into `bc` when the
 // caller owns it for this source (ATOMIC_BC false), with an FP64 atomic add
-// otherwise.
+// otherwise; not at all when `bc` is null (the caller adds the dependencies
+// later, in one streaming pass).
 template <bool PACKED, int SCOPE, bool ATOMIC_BC>
 __device__ __forceinline__ void delta_round(const DevGraph &g, const Slab &S, const RoundCtx &c, double *bc)
 {
@@ -741,7 +742,7 @@ __device__ __forceinline__ void delta_round(const DevGraph &g, const Slab &S, co
             }
             if (ready) {
                 store_f64<SCOPE>(&S.delta[v], acc);
-                if (v != c.s) {
+                if (bc && v != c.s) {
                     const int32_t o = c.perm ? c.perm[v] : v;
                     if (ATOMIC_BC)
                         unsafeAtomicAdd(&bc[o], acc);
@@ -784,7 +785,7 @@ __device__ __forceinline__ void delta_round(const DevGraph &g, const Slab &S, co
             acc = wave_sum_f64(acc);
             if (all_ready && lane == 0) {
                 store_f64<SCOPE>(&S.delta[hv], acc);
-                if (hv != c.s) {
+                if (bc && hv != c.s) {
                     const int32_t o = c.perm ? c.perm[hv] : hv;
                     if (ATOMIC_BC)
                         unsafeAtomicAdd(&bc[o], acc);
@@ -845,7 +846,7 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             pe = g.trow[w + 1];
             dw = load_f64<SCOPE>(&S.delta[w]);
             sw = (double)S.sigma[w];
-            if (w != c.s) {
+            if (bc && w != c.s) {
                 const int32_t o = c.perm ? c.perm[w] : w;
                 if (ATOMIC_BC)
                     unsafeAtomicAdd(&bc[o], dw);
