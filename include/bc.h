@@ -131,7 +131,7 @@ typedef struct {
                              shortest-path DAG recorded by the count pass (Kahn's order),
                              2 = pull over out-arcs band by band in reverse */
     int32_t virtual_warp; /* frontier expansion: 0 = by degree, one lane per vertex up to 8
-                             arcs, a group of 8 lanes up to 128, a whole wave above;
+                             arcs, a group of 8 lanes up to 64, a whole wave above;
                              1, 2, 4, ..., 64 = a fixed group of that many lanes per vertex
                              (the warp-centric mapping of Sec. 3.4) */
     int32_t node_parallel;/* batched frontier expansion: 0 = over the queue (work-efficient,

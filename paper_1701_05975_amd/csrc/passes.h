@@ -129,13 +129,19 @@ struct ExpandCtx {
 // Arcs handled per step by a lane that walks its own row: their heads and
 // the heads' distances are loaded together, so several independent loads per
 // lane are in flight instead of one dependent chain per arc.
-#define LANE_UNROLL 4
+#ifndef LANE_UNROLL
+#define LANE_UNROLL 2
+#endif
 
 // Adaptive expansion (Sec. 3.4's degree-aware mapping, three tiers): a vertex
 // with at most EXPAND_GROUP arcs is walked by one lane, one with at most
 // EXPAND_WAVE_DEG by a group of EXPAND_GROUP lanes, a larger one by the wave.
+#ifndef EXPAND_GROUP
 #define EXPAND_GROUP 8
-#define EXPAND_WAVE_DEG 128
+#endif
+#ifndef EXPAND_WAVE_DEG
+#define EXPAND_WAVE_DEG 64
+#endif
 
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
