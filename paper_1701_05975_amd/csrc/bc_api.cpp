@@ -714,6 +714,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
         a.lds16 = r.lds_bits == 16;
+        a.hubs = g->maxdeg > BC_HUB_DEG;
         a.kahn = r.dep_mode == 1 ? 1 : 0;
         a.vw = r.vw;
         a.node_parallel = r.node_parallel;

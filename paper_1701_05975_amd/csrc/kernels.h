@@ -21,6 +21,7 @@ struct BatchArgs {
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
     int32_t lds16;                // LDS entries are 16-bit (65535 = kept in the slab)
+    int32_t hubs;                 // the graph has vertices of more than BC_HUB_DEG arcs
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
     int32_t vw;                   // expansion: 0 adaptive lane/wave, else lanes per vertex
     int32_t node_parallel;        // expansion scans every vertex instead of the queue

@@ -32,6 +32,8 @@ __device__ __forceinline__ uint32_t sat_add_u32(uint32_t x, uint64_t y)
 struct WgCtl {
     int near_len, next_cnt, order_cnt, far_cnt, kept_cnt, pend_cnt;
     int outer_cnt, okept_cnt, resplit;
+    int huge_cnt;
+    int32_t huge_q[EXPAND_WG_CAP]; // hubs of the current pass, expanded by the workgroup
     int cur, fcur, ocur;
     int32_t gen, band_gen;
     uint32_t thr, thr_old, far_min, bound, outer_min;
@@ -210,6 +212,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             C.far_cnt = 0;
             C.outer_cnt = 0;
             C.ocur = 0;
+            C.huge_cnt = 0;
             C.band_gen = C.gen;
             C.thr = a.delta;
             C.far_min = BC_INF;
@@ -247,8 +250,26 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ec.bound = C.bound;
                 ec.outer_q = C.ocur ? S.ob : S.oa;
                 ec.outer_cnt = &C.outer_cnt;
+                const bool hubs = a.hubs && !a.vw;
+                ec.huge_q = hubs ? C.huge_q : nullptr;
+                ec.huge_cnt = &C.huge_cnt;
                 uint32_t fmin = BC_INF, omin = BC_INF;
                 expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, omin, st_imp);
+                if (hubs) {
+                    __syncthreads();
+                    // the listed hubs, each by the whole workgroup
+                    const int nh = C.huge_cnt < EXPAND_WG_CAP ? C.huge_cnt : EXPAND_WG_CAP;
+                    for (int h = 0; h < nh; ++h) {
+                        const int32_t v = C.huge_q[h];
+                        const uint32_t hb = g.row[v], he = g.row[v + 1];
+                        const uint32_t hd = dist_get(S, v);
+                        for (uint32_t e = hb + tid; e < he; e += NT) {
+                            uint32_t u, w;
+                            arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
+                            relax<WG_SCOPE>(S, ec, u, hd + w, dist_get(S, u), fmin, omin, st_imp);
+                        }
+                    }
+                }
                 fmin = wave_min_u32(fmin);
                 omin = wave_min_u32(omin);
                 if (lane == 0 && fmin != BC_INF)
@@ -260,6 +281,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                     C.cur ^= 1;
                     C.near_len = C.next_cnt;
                     C.next_cnt = 0;
+                    C.huge_cnt = 0;
                     C.gen += 1;
                     if (++C.iters > iter_cap) {
                         C.abort = 1;
@@ -649,6 +671,8 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.bound = BC_INF; // one far pile: the whole grid scans it per band
         ec.outer_q = nullptr;
         ec.outer_cnt = nullptr;
+        ec.huge_q = nullptr; // a hub is one wave's work here (the grid is the team)
+        ec.huge_cnt = nullptr;
         uint32_t fmin = BC_INF, omin = BC_INF;
         uint64_t imp = 0;
         expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, omin, imp);

@@ -124,6 +124,8 @@ struct ExpandCtx {
     uint32_t bound;       // far values at or above go to the outer pile (BC_INF: none)
     int32_t *outer_q;
     int *outer_cnt;
+    int32_t *huge_q;      // optional: vertices with more than EXPAND_WG_DEG arcs are listed
+    int *huge_cnt;        // here for the whole workgroup to expand after the pass
 };
 
 // Arcs handled per step by a lane that walks its own row: their heads and
@@ -142,6 +144,12 @@ struct ExpandCtx {
 #ifndef EXPAND_WAVE_DEG
 #define EXPAND_WAVE_DEG 64
 #endif
+// Fourth tier (batched form): a vertex with more than EXPAND_WG_DEG arcs is
+// expanded by every thread of the workgroup after the pass, so that one hub
+// does not keep one wave busy while the others wait at the barrier.  The list
+// holds EXPAND_WG_CAP vertices; further ones take the wave path.
+#define EXPAND_WG_DEG BC_HUB_DEG
+#define EXPAND_WG_CAP 256
 
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
@@ -246,7 +254,15 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
         const uint32_t deg = end - beg;
         const bool light = valid && deg <= (uint32_t)EXPAND_GROUP;
         const bool mid = valid && deg > (uint32_t)EXPAND_GROUP && deg <= (uint32_t)EXPAND_WAVE_DEG;
-        const bool heavy = valid && deg > (uint32_t)EXPAND_WAVE_DEG;
+        bool heavy = valid && deg > (uint32_t)EXPAND_WAVE_DEG;
+        if (c.huge_q) {
+            const bool huge = heavy && deg > (uint32_t)EXPAND_WG_DEG;
+            const int k = wave_alloc(c.huge_cnt, huge);
+            if (huge && k < EXPAND_WG_CAP) {
+                c.huge_q[k] = c.all_vertices ? i : c.items[i];
+                heavy = false;
+            }
+        }
         if (light) {
             for (uint32_t e0 = beg; e0 < end; e0 += LANE_UNROLL) {
                 uint32_t u[LANE_UNROLL], w[LANE_UNROLL], du[LANE_UNROLL];

@@ -177,6 +177,7 @@ class HipExec {
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
         a.lds16 = c->lds16;
+        a.hubs = g->maxdeg > BC_HUB_DEG;
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.ebc = nullptr;
         a.emap = nullptr;

@@ -6,6 +6,9 @@
 
 #define BC_INF 0x7fffffffu
 #define WAVE 64
+// Batched expansion: vertices with more arcs than this are expanded by the
+// whole workgroup (only graphs that have such a vertex pay for the step).
+#define BC_HUB_DEG 512
 
 // ---------------------------------------------------------------------------
 // Graph as seen by the kernels.
