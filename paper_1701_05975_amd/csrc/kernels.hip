@@ -21,7 +21,9 @@
 // ---------------------------------------------------------------------------
 // Far values this many band widths or more beyond the threshold wait in the
 // outer pile, which is scanned only when the threshold passes its bound.
+#ifndef OUTER_BANDS
 #define OUTER_BANDS 16
+#endif
 
 __device__ __forceinline__ uint32_t sat_add_u32(uint32_t x, uint64_t y)
 {
@@ -88,6 +90,7 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
         rc.err = a.err;
         rc.item_err = a.item_err;
         rc.perm = ATOMIC_BC ? a.perm : nullptr;
+        rc.keys = a.ebc == nullptr;
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE, RECORD>(g, S, rc, st_arcs, st_dag);
         else
@@ -193,6 +196,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 S.sigma[v] = 0;
                 if (a.kahn)
                     S.scnt[v] = 0;
+                if (a.ebc == nullptr) { // predecessor keys and tie flags start empty
+                    *key_ptr(S, v) = KEY_NONE;
+                    S.infar[v] = 0;
+                }
             }
         }
         __syncthreads();
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 const bool hubs = a.hubs && !a.vw;
                 ec.huge_q = hubs ? C.huge_q : nullptr;
                 ec.huge_cnt = &C.huge_cnt;
+                ec.keys = a.ebc == nullptr;
                 uint32_t fmin = BC_INF, omin = BC_INF;
                 expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, omin, st_imp);
                 if (hubs) {
@@ -266,7 +274,8 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                         for (uint32_t e = hb + tid; e < he; e += NT) {
                             uint32_t u, w;
                             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                            relax<WG_SCOPE>(S, ec, u, hd + w, dist_get(S, u), fmin, omin, st_imp);
+                            relax<WG_SCOPE>(S, ec, u, hd + w, dist_get(S, u), (uint32_t)v, fmin,
+                                            omin, st_imp);
                         }
                     }
                 }
@@ -673,6 +682,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.outer_cnt = nullptr;
         ec.huge_q = nullptr; // a hub is one wave's work here (the grid is the team)
         ec.huge_cnt = nullptr;
+        ec.keys = 0;
         uint32_t fmin = BC_INF, omin = BC_INF;
         uint64_t imp = 0;
         expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, omin, imp);
@@ -722,6 +732,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.err = a.err;
         rc.item_err = nullptr;
         rc.perm = a.perm;
+        rc.keys = 0; // the plain form records no predecessor keys
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
             sigma_round<PACKED, AG_SCOPE, false>(g, S, rc, arcs, dag);

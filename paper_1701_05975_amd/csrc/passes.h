@@ -126,7 +126,25 @@ struct ExpandCtx {
     int *outer_cnt;
     int32_t *huge_q;      // optional: vertices with more than EXPAND_WG_DEG arcs are listed
     int *huge_cnt;        // here for the whole workgroup to expand after the pass
+    int keys;             // record each vertex's (distance, predecessor) key and ties
 };
+
+// Predecessor keys (batched form).  While distances are being found, the
+// dependency field of a vertex (unused until its count is taken) holds the
+// least (distance << 32 | tail) over the improvements it received, and
+// VFLAG_TIE in its far-flags word marks that some relaxation matched its
+// distance at the time.  A vertex whose final distance is the key's and that
+// never saw a tie has exactly one shortest-path predecessor, the key's tail:
+// every arc that is tight for the final distances is relaxed with its tail's
+// final distance, the first such relaxation improves and any further one
+// ties, and no vertex is expanded twice at the same distance.
+#define VFLAG_TIE 4
+#define KEY_NONE (~0ull)
+
+__device__ __forceinline__ uint64_t *key_ptr(const Slab &S, int32_t v)
+{
+    return reinterpret_cast<uint64_t *>(&S.delta[v]);
+}
 
 // Arcs handled per step by a lane that walks its own row: their heads and
 // the heads' distances are loaded together, so several independent loads per
@@ -153,13 +171,21 @@ struct ExpandCtx {
 
 template <int SCOPE>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
-                                      uint32_t du, uint32_t &far_min, uint32_t &outer_min,
-                                      uint64_t &nimp)
+                                      uint32_t du, uint32_t tail, uint32_t &far_min,
+                                      uint32_t &outer_min, uint64_t &nimp)
 {
-    bool imp = false;
+    bool imp = false, tie = nd == du;
     if (nd < du) {
         uint32_t old = dist_min<SCOPE>(S, u, nd);
         imp = nd < old;
+        tie = nd == old;
+    }
+    if (c.keys) {
+        if (imp)
+            __hip_atomic_fetch_min(key_ptr(S, (int32_t)u), (uint64_t)nd << 32 | tail,
+                                   __ATOMIC_RELAXED, SCOPE);
+        if (tie)
+            atomic_or_i32<SCOPE>(&S.infar[u], VFLAG_TIE);
     }
     bool pn = false, pm = false, pf = false, po = false;
     if (imp) {
@@ -222,7 +248,7 @@ __device__ __forceinline__ void expand_pass_vw(const DevGraph &g, const Slab &S,
         for (uint32_t e = beg + sub; e < end; e += W) {
             uint32_t u, w;
             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-            relax<SCOPE>(S, c, u, dv + w, dist_get(S, u), far_min, outer_min, nimp);
+            relax<SCOPE>(S, c, u, dv + w, dist_get(S, u), (uint32_t)v, far_min, outer_min, nimp);
         }
     }
 }
@@ -241,8 +267,9 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
         const int i = base + lane;
         bool valid = i < len;
         uint32_t beg = 0, end = 0, dv = BC_INF;
+        int v = 0;
         if (valid) {
-            const int v = c.all_vertices ? i : c.items[i];
+            v = c.all_vertices ? i : c.items[i];
             if (c.all_vertices)
                 valid = S.stamp[v] == c.cur_tag;
             if (valid) {
@@ -259,7 +286,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             const bool huge = heavy && deg > (uint32_t)EXPAND_WG_DEG;
             const int k = wave_alloc(c.huge_cnt, huge);
             if (huge && k < EXPAND_WG_CAP) {
-                c.huge_q[k] = c.all_vertices ? i : c.items[i];
+                c.huge_q[k] = v;
                 heavy = false;
             }
         }
@@ -279,7 +306,8 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
 #pragma unroll
                 for (int j = 0; j < LANE_UNROLL; ++j)
                     if (e0 + j < end)
-                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], far_min, outer_min, nimp);
+                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], (uint32_t)v, far_min, outer_min,
+                                     nimp);
             }
         }
         // Medium degree: up to WAVE / EXPAND_GROUP vertices at a time, one per
@@ -298,6 +326,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             const uint32_t mb = (uint32_t)__shfl((int)beg, l);
             const uint32_t me0 = (uint32_t)__shfl((int)end, l);
             const uint32_t md = (uint32_t)__shfl((int)dv, l);
+            const uint32_t mv = (uint32_t)__shfl(v, l);
             const uint32_t me = have ? me0 : mb;
             constexpr int G = EXPAND_GROUP;
             for (uint32_t e0 = mb + sub; e0 < me; e0 += G * 2) {
@@ -315,7 +344,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     if (e0 + G * j < me)
-                        relax<SCOPE>(S, c, u[j], md + w[j], du[j], far_min, outer_min, nimp);
+                        relax<SCOPE>(S, c, u[j], md + w[j], du[j], mv, far_min, outer_min, nimp);
             }
         }
         uint64_t hm = __ballot(heavy);
@@ -325,10 +354,11 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             const uint32_t hb = (uint32_t)__shfl((int)beg, l);
             const uint32_t he = (uint32_t)__shfl((int)end, l);
             const uint32_t hd = (uint32_t)__shfl((int)dv, l);
+            const uint32_t hv = (uint32_t)__shfl(v, l);
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), far_min, outer_min, nimp);
+                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), hv, far_min, outer_min, nimp);
             }
         }
     }
@@ -453,6 +483,7 @@ struct RoundCtx {
     unsigned int *item_err;  // optional per-source-entry overflow flags
     const int32_t *perm;     // optional: caller's vertex id of each internal vertex, used
                              // when adding into a caller-indexed output
+    int keys;                // predecessor keys were recorded (count pass shortcut)
 };
 
 __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
@@ -497,11 +528,35 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
             if (RECORD && end > beg)
                 S.preds[beg] = -1;
         }
-        const uint32_t deg = end - beg;
-        const bool heavy = valid && !is_src && deg > (uint32_t)EXPAND_WAVE_DEG;
-        const bool mid = valid && !is_src && !heavy && deg > (uint32_t)c.lane_max;
         bool pend = false;
-        if (valid && !is_src && !heavy && !mid) {
+        // A vertex with a single recorded predecessor takes its count from it
+        // (see key_ptr); the others scan their in-arcs below.
+        bool keyed = false;
+        if (c.keys && valid && !is_src) {
+            const uint64_t key = load_u64<SCOPE>(key_ptr(S, v));
+            if (!(S.infar[v] & VFLAG_TIE) && (uint32_t)(key >> 32) == dist_get(S, v)) {
+                keyed = true;
+                const int32_t u = (int32_t)(uint32_t)key;
+                const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                if (su == 0) {
+                    pend = true;
+                } else {
+                    store_u64<SCOPE>(&S.sigma[v], su);
+                    store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
+                    dag += 1;
+                    if (RECORD) {
+                        S.preds[beg] = -(u + 2); // a vertex, not an in-row position
+                        if (beg + 1 < end)
+                            S.preds[beg + 1] = -1;
+                        __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+                    }
+                }
+            }
+        }
+        const uint32_t deg = end - beg;
+        const bool heavy = valid && !is_src && !keyed && deg > (uint32_t)EXPAND_WAVE_DEG;
+        const bool mid = valid && !is_src && !keyed && !heavy && deg > (uint32_t)c.lane_max;
+        if (valid && !is_src && !keyed && !heavy && !mid) {
             const uint32_t dv = dist_get(S, v);
             uint64_t acc = 0;
             bool ready = true, ovf = false;
@@ -851,6 +906,18 @@ __device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double
     return __hip_atomic_fetch_sub(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE) == 1;
 }
 
+// A recorded predecessor: an in-row position (>= 0, decoded through the
+// in-arcs) or a vertex stored as -(u + 2) by the count pass shortcut.
+template <bool PACKED>
+__device__ __forceinline__ int32_t pred_vertex(const DevGraph &g, int32_t pos)
+{
+    if (pos < 0)
+        return -(pos + 2);
+    uint32_t u, w;
+    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, u, w);
+    return (int32_t)u;
+}
+
 template <bool PACKED, int SCOPE, bool ATOMIC_BC>
 __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, const KahnCtx &c, double *bc)
 {
@@ -884,11 +951,9 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             uint32_t j = pb;
             for (; j < lim; ++j) {
                 const int32_t pos = S.preds[j];
-                if (pos < 0)
+                if (pos == -1)
                     break;
-                uint32_t uu, wgt;
-                arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, uu, wgt);
-                const int32_t u = (int32_t)uu;
+                const int32_t u = pred_vertex<PACKED>(g, pos);
                 const double term = (double)S.sigma[u] / sw * (1.0 + dw);
                 if (c.ebc) // the term is the source's dependency on the arc u -> w
                     unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
@@ -911,14 +976,12 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             for (uint32_t e0 = hb; e0 < he; e0 += WAVE) {
                 const uint32_t e = e0 + lane;
                 const int32_t pos = e < he ? S.preds[e] : -1;
-                const uint64_t endm = __ballot(pos < 0);
+                const uint64_t endm = __ballot(pos == -1);
                 const int stop = endm ? __ffsll((unsigned long long)endm) - 1 : WAVE;
                 bool fin = false;
                 int32_t u = 0;
                 if (lane < stop) {
-                    uint32_t uu, wgt;
-                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, uu, wgt);
-                    u = (int32_t)uu;
+                    u = pred_vertex<PACKED>(g, pos);
                     const double term = (double)S.sigma[u] / hs * (1.0 + hd);
                     if (c.ebc)
                         unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
