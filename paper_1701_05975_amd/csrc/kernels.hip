@@ -196,10 +196,9 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 S.sigma[v] = 0;
                 if (a.kahn)
                     S.scnt[v] = 0;
-                if (a.ebc == nullptr) { // predecessor keys and tie flags start empty
-                    *key_ptr(S, v) = KEY_NONE;
-                    S.infar[v] = 0;
-                }
+                S.infar[v] = 0; // far-pile and tie flags start clear
+                if (a.ebc == nullptr)
+                    *key_ptr(S, v) = KEY_NONE; // no predecessor key yet
             }
         }
         __syncthreads();
@@ -393,6 +392,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 sp.order_cnt = &C.order_cnt;
                 sp.far_out = C.fcur ? S.fa : S.fb;
                 sp.kept_cnt = &C.kept_cnt;
+                sp.clear_flags = 0;
                 uint32_t kmin = BC_INF;
                 split_pass(S, sp, kmin);
                 kmin = wave_min_u32(kmin);
@@ -711,6 +711,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         sp.order_cnt = &c->order_cnt;
         sp.far_out = c->fcur ? S.fa : S.fb;
         sp.kept_cnt = &c->kept_cnt;
+        sp.clear_flags = 1;
         uint32_t kmin = BC_INF;
         split_pass(S, sp, kmin);
         kmin = wave_min_u32(kmin);

@@ -382,6 +382,10 @@ struct SplitCtx {
     int *order_cnt;
     int32_t *far_out;
     int *kept_cnt;
+    int clear_flags; // clear the pile flag of entries leaving the pile (else the
+                     // caller clears every flag before the next source: a vertex
+                     // that left the pile never returns to it, as its distance
+                     // is now below the threshold and only decreases)
 };
 
 __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uint32_t &kept_min)
@@ -399,7 +403,7 @@ __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uin
         const bool drop = valid && dv < c.thr_old;
         const bool move = valid && !drop && dv < c.thr;
         const bool keep = valid && !drop && !move;
-        if (drop || move)
+        if (c.clear_flags && (drop || move))
             S.infar[v] &= ~1; // each vertex sits at most once in a pile
         if (move)
             S.stamp[v] = c.tag;
@@ -419,7 +423,9 @@ __device__ __forceinline__ void split_pass(const Slab &S, const SplitCtx &c, uin
 
 // Outer pile pass, when the band threshold has passed the pile bound: entries
 // already settled are dropped, entries below the new bound join the inner
-// pile (unless already there), the rest stay in the outer pile.
+// pile (unless already there), the rest stay in the outer pile.  Flags of
+// entries leaving the outer pile are left set (they never return to it; the
+// caller clears every flag before the next source).
 struct OuterSplitCtx {
     const int32_t *outer_in;
     int len;
@@ -450,8 +456,8 @@ __device__ __forceinline__ void outer_split_pass(const Slab &S, const OuterSplit
         const bool move = valid && !drop && dv < c.bound;
         const bool keep = valid && !drop && !move;
         const bool join = move && !(f & 1);
-        if (drop || move)
-            S.infar[v] = (f & ~2) | (join ? 1 : 0);
+        if (join)
+            S.infar[v] = f | 1;
         if (keep)
             kept_min = dv < kept_min ? dv : kept_min;
         int k = wave_alloc(c.inner_cnt, join);
