@@ -37,6 +37,7 @@ struct Slab {
     VField<int32_t, VREC_STAMP> stamp;
     VField<int32_t, VREC_INFAR> infar;
     VField<int32_t, VREC_SCNT> scnt;
+    VField<int32_t, VREC_PRED1> pred1;
     VField<uint64_t, VREC_SIGMA> sigma;
     VField<double, VREC_DELTA> delta;
     double *bcp;       // per-slab partial centrality (batched form)
@@ -58,7 +59,7 @@ __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slo
     char *p = base + (size_t)slot * L.stride;
     Slab s;
     s.d = (uint32_t *)(p + L.d);
-    s.stamp.rec = s.infar.rec = s.scnt.rec = s.sigma.rec = s.delta.rec = p + L.rec;
+    s.stamp.rec = s.infar.rec = s.scnt.rec = s.pred1.rec = s.sigma.rec = s.delta.rec = p + L.rec;
     s.bcp = (double *)(p + L.bcp);
     s.order = (int32_t *)(p + L.order);
     s.qa = (int32_t *)(p + L.qa);

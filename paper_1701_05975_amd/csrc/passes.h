@@ -531,8 +531,11 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
         if (is_src) {
             // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
             store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
-            if (RECORD && end > beg)
-                S.preds[beg] = -1;
+            if (RECORD) {
+                S.pred1[v] = -1;
+                if (end > beg)
+                    S.preds[beg] = -1;
+            }
         }
         bool pend = false;
         // A vertex with a single recorded predecessor takes its count from it
@@ -551,9 +554,7 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                     store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                     dag += 1;
                     if (RECORD) {
-                        S.preds[beg] = -(u + 2); // a vertex, not an in-row position
-                        if (beg + 1 < end)
-                            S.preds[beg + 1] = -1;
+                        S.pred1[v] = u; // in the record: no DAG list to write or read
                         __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
                     }
                 }
@@ -605,6 +606,7 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                 dag += tight;
                 if (RECORD) {
+                    S.pred1[v] = -1;
                     if (beg + tight < end)
                         S.preds[beg + tight] = -1;
                     for (uint32_t j = 0; j < tight; ++j) {
@@ -688,8 +690,11 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_u64<SCOPE>(&S.sigma[mv], acc);
                 store_f64<SCOPE>(&S.delta[mv], RECORD ? 0.0 : -1.0);
                 dag += rec;
-                if (RECORD && mb + rec < me)
-                    S.preds[mb + rec] = -1;
+                if (RECORD) {
+                    S.pred1[mv] = -1;
+                    if (mb + rec < me)
+                        S.preds[mb + rec] = -1;
+                }
             }
             if (RECORD && have && gready)
                 for (uint32_t j = sub; j < rec; j += EXPAND_GROUP) {
@@ -753,8 +758,11 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_u64<SCOPE>(&S.sigma[hv], acc);
                 store_f64<SCOPE>(&S.delta[hv], RECORD ? 0.0 : -1.0);
                 dag += tight;
-                if (RECORD && hb + tight < he)
-                    S.preds[hb + tight] = -1;
+                if (RECORD) {
+                    S.pred1[hv] = -1;
+                    if (hb + tight < he)
+                        S.preds[hb + tight] = -1;
+                }
             }
             if (RECORD && all_ready)
                 for (uint32_t j = lane; j < tight; j += WAVE) {
@@ -912,13 +920,10 @@ __device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double
     return __hip_atomic_fetch_sub(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE) == 1;
 }
 
-// A recorded predecessor: an in-row position (>= 0, decoded through the
-// in-arcs) or a vertex stored as -(u + 2) by the count pass shortcut.
+// A recorded predecessor: the tail of the in-arc at in-row position pos.
 template <bool PACKED>
 __device__ __forceinline__ int32_t pred_vertex(const DevGraph &g, int32_t pos)
 {
-    if (pos < 0)
-        return -(pos + 2);
     uint32_t u, w;
     arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, u, w);
     return (int32_t)u;
@@ -932,11 +937,12 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
     for (int base = c.worker * WAVE; base < c.len; base += c.nworkers * WAVE) {
         const int i = base + lane;
         const bool valid = i < c.len;
-        int32_t w = 0;
+        int32_t w = 0, p1 = -1;
         uint32_t pb = 0, pe = 0;
         double dw = 0.0, sw = 1.0;
         if (valid) {
             w = c.items[i];
+            p1 = S.pred1[w];
             pb = g.trow[w];
             pe = g.trow[w + 1];
             dw = load_f64<SCOPE>(&S.delta[w]);
@@ -952,7 +958,13 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
         // A lane walks up to lane_max recorded predecessors; the rest of a
         // longer list is finished by the whole wave.
         bool more = false;
-        if (valid) {
+        if (valid && p1 >= 0) { // the only predecessor, kept in the record
+            const double term = (double)S.sigma[p1] / sw * (1.0 + dw);
+            const bool fin = push_dependency<SCOPE>(S, p1, term);
+            const int k = wave_alloc(c.next_cnt, fin);
+            if (fin)
+                c.next_q[k] = p1;
+        } else if (valid) {
             const uint32_t lim = pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
             uint32_t j = pb;
             for (; j < lim; ++j) {

@@ -45,6 +45,7 @@ struct DevGraph {
 #define VREC_STAMP 0  // i32 tag of the latest near queue the vertex entered
 #define VREC_INFAR 4  // i32 bit 0: in the inner far pile; bit 1: in the outer far pile
 #define VREC_SCNT 8   // i32 shortest-path-DAG successors not yet accumulated
+#define VREC_PRED1 12 // i32 the only DAG predecessor, or -1: the list in preds[]
 #define VREC_SIGMA 16 // u64 shortest-path count (0 = not yet final in the count pass)
 #define VREC_DELTA 24 // f64 dependency (negative = not yet final in the pull pass)
 
