@@ -959,7 +959,8 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
         // longer list is finished by the whole wave.
         bool more = false;
         if (valid && p1 >= 0) { // the only predecessor, kept in the record
-            const double term = (double)S.sigma[p1] / sw * (1.0 + dw);
+            // sigma[w] was copied from sigma[p1], so their ratio is exactly 1
+            const double term = 1.0 + dw;
             const bool fin = push_dependency<SCOPE>(S, p1, term);
             const int k = wave_alloc(c.next_cnt, fin);
             if (fin)
