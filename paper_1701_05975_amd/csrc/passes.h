@@ -4,10 +4,13 @@
 // of the grid and counters in global memory.
 //
 // Mapping of vertices to lanes (the warp-centric idea of Sec. 3.4 recast for
-// 64-lane wavefronts): a vertex with at most `lane_max` arcs is handled by
-// one lane, which walks its arcs in order; a vertex with more arcs is handled
-// by the whole wave, the 64 lanes striding over its arcs together.  Only
-// queued vertices get lanes (the work-efficient queue of Sec. 3.3).
+// 64-lane wavefronts), by degree: a low-degree vertex is handled by one lane,
+// which walks its arcs in order; a medium one by a group of EXPAND_GROUP
+// lanes; a large one by the whole wave, the 64 lanes striding over its arcs
+// together (and in the batched expansion a hub by the whole workgroup).  Only
+// queued vertices get lanes (the work-efficient queue of Sec. 3.3); a fixed
+// group width and a scan over every vertex (node-parallel) are selectable for
+// comparison.
 #pragma once
 
 #include "dev_common.h"
