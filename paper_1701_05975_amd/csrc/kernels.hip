@@ -91,6 +91,7 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
         rc.item_err = a.item_err;
         rc.perm = ATOMIC_BC ? a.perm : nullptr;
         rc.keys = a.ebc == nullptr;
+        rc.band_gen = C.band_gen;
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE, RECORD>(g, S, rc, st_arcs, st_dag);
         else
@@ -423,46 +424,54 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 }
             }
         }
+        // Kahn's order band by band, last band first: successor counts cover
+        // only arcs inside a band, and a vertex's successors in later bands
+        // are all done before its own band starts.
         if (!C.abort && a.kahn) {
-            if (tid == 0)
-                C.pend_cnt = 0;
-            __syncthreads();
-            kahn_leaves(S, S.order, C.order_cnt, tid / WAVE, NT / WAVE, S.qa, &C.pend_cnt);
-            __syncthreads();
-            int len = C.pend_cnt;
-            __syncthreads();
-            const int32_t *items = S.qa;
-            int which = 0;
             const int cap = C.order_cnt + 2;
-            for (int step = 0; len > 0; ++step) {
-                if (step > cap) {
-                    if (tid == 0)
-                        C.abort = 1;
-                    break;
-                }
+            int steps = 0;
+            for (int b = C.nbands - 1; b >= 0 && !C.abort; --b) {
+                const int b0 = S.band_off[b], b1 = S.band_off[b + 1];
                 if (tid == 0)
                     C.pend_cnt = 0;
                 __syncthreads();
-                KahnCtx kc;
-                kc.items = items;
-                kc.len = len;
-                kc.worker = tid / WAVE;
-                kc.nworkers = NT / WAVE;
-                kc.lane_max = a.lane_max;
-                kc.s = s;
-                kc.next_q = which ? S.qa : S.qb;
-                kc.next_cnt = &C.pend_cnt;
-                kc.perm = ATOMIC_BC ? a.perm : nullptr;
-                kc.ebc = a.ebc;
-                kc.emap = a.emap;
-                kahn_step<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, kc, bc);
+                kahn_leaves(S, S.order + b0, b1 - b0, tid / WAVE, NT / WAVE, S.qa, &C.pend_cnt);
                 __syncthreads();
-                len = C.pend_cnt;
+                int len = C.pend_cnt;
                 __syncthreads();
-                items = which ? S.qa : S.qb;
-                which ^= 1;
-                if (tid == 0)
-                    C.drounds++;
+                const int32_t *items = S.qa;
+                int which = 0;
+                while (len > 0) {
+                    if (++steps > cap) {
+                        if (tid == 0)
+                            C.abort = 1;
+                        __syncthreads();
+                        break;
+                    }
+                    if (tid == 0)
+                        C.pend_cnt = 0;
+                    __syncthreads();
+                    KahnCtx kc;
+                    kc.items = items;
+                    kc.len = len;
+                    kc.worker = tid / WAVE;
+                    kc.nworkers = NT / WAVE;
+                    kc.lane_max = a.lane_max;
+                    kc.s = s;
+                    kc.next_q = which ? S.qa : S.qb;
+                    kc.next_cnt = &C.pend_cnt;
+                    kc.perm = ATOMIC_BC ? a.perm : nullptr;
+                    kc.ebc = a.ebc;
+                    kc.emap = a.emap;
+                    kahn_step<PACKED, WG_SCOPE, ATOMIC_BC>(g, S, kc, bc);
+                    __syncthreads();
+                    len = C.pend_cnt;
+                    __syncthreads();
+                    items = which ? S.qa : S.qb;
+                    which ^= 1;
+                    if (tid == 0)
+                        C.drounds++;
+                }
             }
         }
         phase_mark(C, tmark, 3);
@@ -734,6 +743,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.item_err = nullptr;
         rc.perm = a.perm;
         rc.keys = 0; // the plain form records no predecessor keys
+        rc.band_gen = 0;
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
             sigma_round<PACKED, AG_SCOPE, false>(g, S, rc, arcs, dag);

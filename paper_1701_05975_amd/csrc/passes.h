@@ -493,6 +493,8 @@ struct RoundCtx {
     const int32_t *perm;     // optional: caller's vertex id of each internal vertex, used
                              // when adding into a caller-indexed output
     int keys;                // predecessor keys were recorded (count pass shortcut)
+    int32_t band_gen;        // queue tag of the band's first pass: a vertex with a tag at
+                             // least this is a member of the band being counted
 };
 
 __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
@@ -510,9 +512,27 @@ __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
 //
 // With RECORD, the in-row positions of the tight in-arcs of v are also
 // written to preds[trow[v] ..] (the slice of v's own in-row, so no allocation
-// is needed), ended by -1 when there are fewer than the in-degree, and every
-// recorded predecessor's successor count scnt is incremented once v is final;
-// the dependency pass then walks this DAG.
+// is needed), ended by -1 when there are fewer than the in-degree; a vertex
+// with a single predecessor keeps it in its record instead.  Successor
+// counts scnt are kept only for DAG arcs inside the band (a predecessor in
+// the same band is stored as -(x + 2)): the dependency pass runs band by band
+// in reverse, so a vertex's successors in later bands are always done before
+// its own band starts.
+// A recorded DAG arc (in-row position at preds[slot]) whose tail lies in the
+// band being counted: count it as a successor of the tail, and mark the entry.
+template <bool PACKED, int SCOPE>
+__device__ __forceinline__ void count_if_same_band(const DevGraph &g, const Slab &S,
+                                                   const RoundCtx &c, uint32_t slot)
+{
+    const int32_t pos = S.preds[slot];
+    uint32_t u, w;
+    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)pos, g.wshift, g.wmask, u, w);
+    if (S.stamp[u] >= c.band_gen) {
+        S.preds[slot] = -(pos + 2);
+        __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+    }
+}
+
 template <bool PACKED, int SCOPE, bool RECORD>
 __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
@@ -550,6 +570,7 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 keyed = true;
                 const int32_t u = (int32_t)(uint32_t)key;
                 const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
+                const bool same = S.stamp[u] >= c.band_gen;
                 if (su == 0) {
                     pend = true;
                 } else {
@@ -557,8 +578,10 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                     store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                     dag += 1;
                     if (RECORD) {
-                        S.pred1[v] = u; // in the record: no DAG list to write or read
-                        __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
+                        // in the record: no DAG list to write or read
+                        S.pred1[v] = same ? -(u + 2) : u;
+                        if (same)
+                            __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
                     }
                 }
             }
@@ -612,12 +635,8 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                     S.pred1[v] = -1;
                     if (beg + tight < end)
                         S.preds[beg + tight] = -1;
-                    for (uint32_t j = 0; j < tight; ++j) {
-                        uint32_t u, w;
-                        arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[beg + j], g.wshift,
-                                       g.wmask, u, w);
-                        __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
-                    }
+                    for (uint32_t j = 0; j < tight; ++j)
+                        count_if_same_band<PACKED, SCOPE>(g, S, c, beg + j);
                 }
             }
             pend = !ready;
@@ -700,12 +719,8 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 }
             }
             if (RECORD && have && gready)
-                for (uint32_t j = sub; j < rec; j += EXPAND_GROUP) {
-                    uint32_t u, w;
-                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[mb + j], g.wshift, g.wmask,
-                                   u, w);
-                    __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
-                }
+                for (uint32_t j = sub; j < rec; j += EXPAND_GROUP)
+                    count_if_same_band<PACKED, SCOPE>(g, S, c, mb + j);
             const bool p = have && !gready && sub == 0;
             const int k = wave_alloc(c.pend_cnt, p);
             if (p)
@@ -768,12 +783,8 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 }
             }
             if (RECORD && all_ready)
-                for (uint32_t j = lane; j < tight; j += WAVE) {
-                    uint32_t u, w;
-                    arc_at<PACKED>(g.tarc, g.twt, (uint32_t)S.preds[hb + j], g.wshift, g.wmask,
-                                   u, w);
-                    __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
-                }
+                for (uint32_t j = lane; j < tight; j += WAVE)
+                    count_if_same_band<PACKED, SCOPE>(g, S, c, hb + j);
             const bool p = !all_ready && lane == 0;
             const int k = wave_alloc(c.pend_cnt, p);
             if (p)
@@ -923,6 +934,18 @@ __device__ __forceinline__ bool push_dependency(const Slab &S, int32_t u, double
     return __hip_atomic_fetch_sub(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE) == 1;
 }
 
+// Adds a dependency term into u.  A predecessor in the same band also has
+// its count of pending successors lowered (true when that reaches zero); one
+// in an earlier band only receives the term, with nothing to wait for.
+template <int SCOPE>
+__device__ __forceinline__ bool push_to(const Slab &S, int32_t u, double c, bool same)
+{
+    if (same)
+        return push_dependency<SCOPE>(S, u, c);
+    __hip_atomic_fetch_add(&S.delta[u], c, __ATOMIC_RELAXED, SCOPE);
+    return false;
+}
+
 // A recorded predecessor: the tail of the in-arc at in-row position pos.
 template <bool PACKED>
 __device__ __forceinline__ int32_t pred_vertex(const DevGraph &g, int32_t pos)
@@ -961,25 +984,27 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
         // A lane walks up to lane_max recorded predecessors; the rest of a
         // longer list is finished by the whole wave.
         bool more = false;
-        if (valid && p1 >= 0) { // the only predecessor, kept in the record
-            // sigma[w] was copied from sigma[p1], so their ratio is exactly 1
+        if (valid && p1 != -1) { // the only predecessor, kept in the record
+            // sigma[w] was copied from sigma[u], so their ratio is exactly 1
             const double term = 1.0 + dw;
-            const bool fin = push_dependency<SCOPE>(S, p1, term);
+            const int32_t u = p1 < 0 ? -(p1 + 2) : p1;
+            const bool fin = push_to<SCOPE>(S, u, term, p1 < 0);
             const int k = wave_alloc(c.next_cnt, fin);
             if (fin)
-                c.next_q[k] = p1;
+                c.next_q[k] = u;
         } else if (valid) {
             const uint32_t lim = pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
             uint32_t j = pb;
             for (; j < lim; ++j) {
-                const int32_t pos = S.preds[j];
-                if (pos == -1)
+                const int32_t raw = S.preds[j];
+                if (raw == -1)
                     break;
+                const int32_t pos = raw < 0 ? -(raw + 2) : raw;
                 const int32_t u = pred_vertex<PACKED>(g, pos);
                 const double term = (double)S.sigma[u] / sw * (1.0 + dw);
                 if (c.ebc) // the term is the source's dependency on the arc u -> w
                     unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
-                const bool fin = push_dependency<SCOPE>(S, u, term);
+                const bool fin = push_to<SCOPE>(S, u, term, raw < 0);
                 const int k = wave_alloc(c.next_cnt, fin);
                 if (fin)
                     c.next_q[k] = u;
@@ -997,17 +1022,18 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             const double hs = __shfl(sw, l);
             for (uint32_t e0 = hb; e0 < he; e0 += WAVE) {
                 const uint32_t e = e0 + lane;
-                const int32_t pos = e < he ? S.preds[e] : -1;
-                const uint64_t endm = __ballot(pos == -1);
+                const int32_t raw = e < he ? S.preds[e] : -1;
+                const uint64_t endm = __ballot(raw == -1);
                 const int stop = endm ? __ffsll((unsigned long long)endm) - 1 : WAVE;
                 bool fin = false;
                 int32_t u = 0;
                 if (lane < stop) {
+                    const int32_t pos = raw < 0 ? -(raw + 2) : raw;
                     u = pred_vertex<PACKED>(g, pos);
                     const double term = (double)S.sigma[u] / hs * (1.0 + hd);
                     if (c.ebc)
                         unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);
-                    fin = push_dependency<SCOPE>(S, u, term);
+                    fin = push_to<SCOPE>(S, u, term, raw < 0);
                 }
                 const int k = wave_alloc(c.next_cnt, fin);
                 if (fin)
@@ -1019,7 +1045,7 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
     }
 }
 
-// Members with no DAG successor start the dependency pass.
+// Members with no DAG successor left in their band start the band's dependency pass.
 __device__ __forceinline__ void kahn_leaves(const Slab &S, const int32_t *order, int n_r, int worker,
                                             int nworkers, int32_t *q, int *cnt)
 {
