@@ -222,7 +222,7 @@ HBM_PEAK_GBS = 8000.0
 TUNED = {
     "ba100k": dict(delta=100, wg_threads=1024, lane_max_deg=16),
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
-    "grid1000": dict(delta=130, wg_threads=512, lane_max_deg=8),
+    "grid1000": dict(delta=91, wg_threads=256, lane_max_deg=128),
     "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
 }
 
