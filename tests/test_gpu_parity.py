@@ -254,6 +254,47 @@ def test_empty_and_degenerate_inputs():
         assert ei.value.status == bc.BC_E_INVAL, bad
 
 
+def hub_graph(directed: bool):
+    """Two hubs of 1500 and 900 arcs (above the workgroup-expansion threshold)
+    over a sparse random graph, with tie-heavy weights."""
+    rng = np.random.default_rng(21 if directed else 22)
+    n = 2500
+    src = [0] * 1500 + [1] * 900
+    dst = list(range(2, 1502)) + list(range(1600, 2500))
+    m = 4000
+    a = rng.integers(0, n, size=m)
+    b = rng.integers(0, n, size=m)
+    keep = a != b
+    src += a[keep].tolist()
+    dst += b[keep].tolist()
+    w = rng.integers(1, 4, size=len(src))
+    if directed:
+        # every leaf also points back, so the hubs have large in-degrees too
+        back_s, back_d = dst[:2400], src[:2400]
+        return gg.csr_from_arcs(n, src + back_s, dst + back_d,
+                                np.concatenate([w, rng.integers(1, 4, size=2400)]), directed=True)
+    pairs = {}
+    for u, v, x in zip(src, dst, w):
+        pairs.setdefault((min(u, v), max(u, v)), int(x))
+    eu = [p[0] for p in pairs]
+    ev = [p[1] for p in pairs]
+    return gg.undirected_from_edges(n, eu, ev, list(pairs.values()))
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_hub_vertices_expanded_by_the_workgroup(directed):
+    g = hub_graph(directed)
+    assert np.diff(g.row_ptr).max() > 512
+    G = bc.Graph(g)
+    want = oracle.oracle_bc(g, np.arange(g.n))
+    for opts in (dict(), dict(wg_threads=256), dict(lds_bits=32), dict(dep_mode=2)):
+        got, _ = G.bc(None, **opts)
+        rel_close(got, want, 1e-9)
+    check_state(g, G, 0)
+    check_state(g, G, 1700)
+    G.close()
+
+
 def test_directed_sinks_and_parallel_arcs():
     # parallel equal-weight arcs are distinct shortest paths; sinks have no arcs
     src = [0, 0, 1, 1, 2, 3, 3]
