@@ -148,7 +148,7 @@ def run_serving(args):
         k = int(np.floor(np.exp(rng.uniform(np.log(64), np.log(4096)))))
         reqs.append((gi, gg.sample_sources(graphs[gi], k, seed=10_000 + i)))
     work = np.array([len(s) * graphs[gi].m for gi, s in reqs], dtype=np.float64)
-    sv = bc.Server()
+    sv = bc.Server(order=args.order)
     # capacity estimate: the warm-up requests served back to back (closed loop)
     warm = args.serve_warmup
     tw = time.perf_counter()
@@ -162,7 +162,7 @@ def run_serving(args):
     print(f"# warm-up: {warm} requests, capacity ~{cap / 1e9:.2f} GTEPS; "
           f"arrival rate {lam:.3f} req/s", file=sys.stderr, flush=True)
     sv.close()
-    sv = bc.Server()
+    sv = bc.Server(order=args.order)
     gaps = np.random.default_rng(201).exponential(1.0 / lam, size=nreq)
     start = time.perf_counter()
     arrivals = start + np.cumsum(gaps)
@@ -209,7 +209,7 @@ def run_serving(args):
         "sweeps": st["sweeps"],
         "mix_vs_alone_max_rel_err": worst,
         "data": "synthetic (seeded generators)",
-        "config": {"workload": f"serving: {WORKLOADS['serving']}", "load": args.load,
+        "config": {"workload": f"serving: {WORKLOADS['serving']}", "load": args.load, "order": "fewest left first" if args.order == 1 else "oldest first",
                    "graphs": [f"{g.name} n={g.n} m={g.m}" for g in graphs]},
     }
     print(json.dumps(rec), flush=True)
@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--ablation-sources", type=int, default=256)
     ap.add_argument("--variants", default="", help="ablation: comma-separated name parts to run")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
+    ap.add_argument("--order", type=int, default=1,
+                    help="serving: 1 = fewest sources left first within a graph, 0 = oldest first")
     ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: fixed arrival rate")

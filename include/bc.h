@@ -275,6 +275,9 @@ typedef struct {
     bc_options compute;           /* delta, lane_max_deg and wg_threads of the sweeps; 0 fields
                                      take the graph's autotuned (else default) values; mode,
                                      batch, accumulate and stream are ignored */
+    int32_t order;                /* which admitted request of a graph a free sweep serves
+                                     first: 0 = the oldest; 1 = the one with the fewest
+                                     sources left (short requests overtake long ones) */
 } bc_server_opts;
 
 typedef struct {

@@ -89,7 +89,7 @@ class bc_server_opts(ctypes.Structure):
     _fields_ = [("result_budget_bytes", ctypes.c_int64), ("slab_bytes_per_sweep", ctypes.c_int64),
                 ("max_active", ctypes.c_int32), ("sweeps_per_graph", ctypes.c_int32),
                 ("slots_per_sweep", ctypes.c_int32), ("items_per_sweep", ctypes.c_int32),
-                ("compute", bc_options)]
+                ("compute", bc_options), ("order", ctypes.c_int32)]
 
 
 class bc_server_stats(ctypes.Structure):
@@ -370,7 +370,7 @@ def bc_server_destroy(sv) -> None:
 
 
 def make_server_opts(result_budget_bytes=0, slab_bytes_per_sweep=0, max_active=0,
-                     sweeps_per_graph=0, slots_per_sweep=0, items_per_sweep=0,
+                     sweeps_per_graph=0, slots_per_sweep=0, items_per_sweep=0, order=0,
                      **compute) -> bc_server_opts:
     o = bc_server_opts()
     o.result_budget_bytes = result_budget_bytes
@@ -379,6 +379,7 @@ def make_server_opts(result_budget_bytes=0, slab_bytes_per_sweep=0, max_active=0
     o.sweeps_per_graph = sweeps_per_graph
     o.slots_per_sweep = slots_per_sweep
     o.items_per_sweep = items_per_sweep
+    o.order = order
     o.compute = make_options(**compute)
     return o
 

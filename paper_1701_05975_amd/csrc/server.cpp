@@ -422,6 +422,8 @@ bc_status bc_server_create(const bc_server_opts *o, bc_server **out)
     try {
         if (!out)
             throw bc_error(BC_E_INVAL, "out is NULL");
+        if (o && (o->order < 0 || o->order > 1))
+            throw bc_error(BC_E_INVAL, "order must be 0 (oldest first) or 1 (fewest left first)");
         int count = 0;
         if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
             (void)hipGetLastError();
@@ -447,6 +449,7 @@ bc_status bc_server_create(const bc_server_opts *o, bc_server **out)
         pol.budget_bytes = (size_t)sv->opts.result_budget_bytes;
         pol.max_active = sv->opts.max_active;
         pol.max_items_per_sweep = 1 << 30; // bounded per context by its buffers below
+        pol.shortest_first = sv->opts.order == 1;
         sv->sched.reset(new bcserve::Scheduler<ExecAdapter>(sv->adapter, pol));
         bc_server *raw = sv.get();
         sv->worker = std::thread([raw] { raw->loop(); });

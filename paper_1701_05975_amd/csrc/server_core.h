@@ -48,6 +48,7 @@ struct Policy {
     size_t budget_bytes = 0;       // device bytes the requests may hold at once
     int max_active = 64;           // admitted, unfinished requests
     int max_items_per_sweep = 1024;
+    bool shortest_first = false;   // within a graph, fewest sources left first (else oldest)
 };
 
 // Executor interface:
@@ -214,11 +215,24 @@ template <class Exec> class Scheduler {
         }
         for (int gidx : graphs) {
             const int cap = std::min(pol_.max_items_per_sweep, ex_.max_items(gidx));
+            // the graph's requests in service order
+            std::vector<uint64_t> serve;
+            for (uint64_t t : order_) {
+                auto r = find(t);
+                if (r && r->graph == gidx)
+                    serve.push_back(t);
+            }
+            if (pol_.shortest_first)
+                std::stable_sort(serve.begin(), serve.end(), [&](uint64_t x, uint64_t y) {
+                    auto rx = find(x), ry = find(y);
+                    return (int64_t)rx->sources.size() - rx->next_item <
+                           (int64_t)ry->sources.size() - ry->next_item;
+                });
             while (ex_.free_contexts(gidx) > 0) {
                 std::vector<SweepItem> items;
-                for (uint64_t t : order_) {
+                for (uint64_t t : serve) {
                     auto r = find(t);
-                    if (!r || r->graph != gidx)
+                    if (!r)
                         continue;
                     while (r->next_item < (int64_t)r->sources.size() &&
                            (int)items.size() < cap) {

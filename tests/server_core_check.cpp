@@ -76,6 +76,22 @@ int main() {
         CHECK(sc.find(c)->phase == ReqPhase::Active);
         CHECK(sc.find(c)->t_admit == 3.0);
     }
+    // 1b. shortest first: a later, shorter request of the same graph is served first
+    {
+        FakeExec ex; ex.cap = 4; ex.ctx_per_graph[0] = 1;
+        Policy p; p.budget_bytes = 1 << 20; p.max_active = 10; p.shortest_first = true;
+        Scheduler<FakeExec> sc(ex, p);
+        uint64_t a = sc.submit(0, s10.data(), 10, 8, 0.0);
+        uint64_t b = sc.submit(0, s3.data(), 3, 8, 0.0);
+        sc.step(0.5);
+        CHECK(ex.running.size() == 1);
+        auto &first = ex.running[0].second;
+        CHECK(first.size() == 4 && first[0].ticket == b && first[2].ticket == b &&
+              first[3].ticket == a);                    // b's 3 sources, then a's first
+        while (!ex.running.empty()) { ex.finish_oldest(); sc.step(1.0); }
+        CHECK(sc.find(b)->phase == ReqPhase::Done && sc.find(a)->phase == ReqPhase::Done);
+        CHECK(sc.find(b)->t_done <= sc.find(a)->t_done);
+    }
     // 2. a request larger than one sweep is split; sweeps per graph bounded; order kept
     {
         FakeExec ex; ex.cap = 4; ex.ctx_per_graph[0] = 2;

@@ -103,3 +103,10 @@ def test_no_device_is_reported_not_faked():
     with pytest.raises(bc.BCError) as ei:
         bc.bc_create_graph(g.n, g.row_ptr, g.col, g.w)
     assert ei.value.status == bc.BC_E_DEVICE
+
+
+def test_server_order_validated_before_device_work():
+    with pytest.raises(bc.BCError) as ei:
+        bc.bc_server_create(bc.make_server_opts(order=2))
+    assert ei.value.status == bc.BC_E_INVAL
+    assert "order" in ei.value.msg
