@@ -222,7 +222,7 @@ HBM_PEAK_GBS = 8000.0
 TUNED = {
     "ba100k": dict(delta=100, wg_threads=1024, lane_max_deg=16),
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
-    "grid1000": dict(delta=91, wg_threads=256, lane_max_deg=128),
+    "grid1000": dict(delta=182, wg_threads=1024, lane_max_deg=128, batch=256),
     "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
 }
 
@@ -361,7 +361,7 @@ def main():
                     lane_max_deg=args.lane_max or pinned.get("lane_max_deg", 0),
                     dep_mode=args.dep_mode or pinned.get("dep_mode", 0),
                     lds_bits=args.lds_bits or pinned.get("lds_bits", 0),
-                    batch=args.batch, accumulate=args.accumulate,
+                    batch=args.batch or pinned.get("batch", 0), accumulate=args.accumulate,
                     stream=stream.cuda_stream)
         base.update(kw)
         return bc.make_options(**base)

@@ -77,8 +77,9 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
                 int H = 0, per_cu = 1;
                 batched_lds_plan(g, nt, t.accumulate == 2, o.lds_vertices, t.lds_bits, H, per_cu);
                 t.lds_vertices = H;
-                t.batch = std::max(1, (int)std::min<int64_t>((int64_t)g->num_cus * per_cu,
-                                                             sample));
+                // a batch the caller fixed stays fixed; else a full occupancy
+                const int64_t want = o.batch ? (int64_t)o.batch : (int64_t)g->num_cus * per_cu;
+                t.batch = std::max(1, (int)std::min<int64_t>(want, sample));
                 const double ms = time_candidate(g, t, src_dev, sample, (double *)scratch.p);
                 if (ms < best) {
                     best = ms;
