@@ -216,15 +216,10 @@ def run_serving(args):
 
 HBM_PEAK_GBS = 8000.0
 
-# Settings the library's autotuner picked for each workload on MI355X
-# (python bench.py --autotune prints them); pinned so that the timed and the
-# profiled command launch identical kernels.
-TUNED = {
-    "ba100k": dict(delta=100, wg_threads=1024, lane_max_deg=16),
-    "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
-    "grid1000": dict(delta=182, wg_threads=1024, lane_max_deg=128, batch=256),
-    "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
-}
+def tuned_settings() -> dict:
+    """Pinned launch settings per workload (shared with the full-size parity tests)."""
+    from paper_1701_05975_amd.launch import LAUNCH
+    return LAUNCH
 
 
 def kernel_source_hash() -> str:
@@ -353,7 +348,7 @@ def main():
                                               eout.data_ptr(), o)
         return bc.bc_compute_device(G.handle, src_dev.data_ptr(), k, out.data_ptr(), o)
 
-    pinned = {} if args.autotune else TUNED.get(args.config, {})
+    pinned = {} if args.autotune else tuned_settings().get(args.config, {})
 
     def opts(**kw):
         base = dict(delta=args.delta or pinned.get("delta", 0),

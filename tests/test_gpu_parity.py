@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from paper_1701_05975_amd import bc, graphgen as gg
+from paper_1701_05975_amd.launch import LAUNCH
 
 pytestmark = pytest.mark.gpu
 
@@ -328,7 +329,7 @@ def test_device_entry_point_with_torch_tensors():
 def test_config_er1000_all_sources():
     g = gg.config_graph("er1000")
     G = bc.Graph(g)
-    for opts in (dict(), dict(mode=bc.BC_MODE_PLAIN), dict(accumulate=2)):
+    for opts in (LAUNCH["er1000"], dict(), dict(mode=bc.BC_MODE_PLAIN), dict(accumulate=2)):
         check_bc(g, G, None, **opts)
     for s in (0, 1, 500, 999):
         check_state(g, G, s)
@@ -338,9 +339,10 @@ def test_config_ba100k_parity_sources():
     g = gg.config_graph("ba100k")
     G = bc.Graph(g)
     srcs = gg.config_sources("ba100k", g, parity=True)
+    check_bc(g, G, srcs, **LAUNCH["ba100k"])  # the benchmark's launch settings
     check_bc(g, G, srcs)
     for s in srcs[:3]:
-        check_state(g, G, int(s))
+        check_state(g, G, int(s), **LAUNCH["ba100k"])
         check_state(g, G, int(s), mode=bc.BC_MODE_PLAIN)
 
 
@@ -351,23 +353,25 @@ def test_config_ba100k_full_launch_linearity():
     g = gg.config_graph("ba100k")
     G = bc.Graph(g)
     allsrc = np.arange(g.n, dtype=np.int32)
-    full, st = G.bc(allsrc)
-    a, _ = G.bc(allsrc[: g.n // 2])
-    b, _ = G.bc(allsrc[g.n // 2:])
+    opts = LAUNCH["ba100k"]
+    full, st = G.bc(allsrc, **opts)
+    a, _ = G.bc(allsrc[: g.n // 2], **opts)
+    b, _ = G.bc(allsrc[g.n // 2:], **opts)
     assert np.all(np.isfinite(full)) and np.all(full >= 0)
     rel_close(full, a + b, 1e-9)
     assert st["reached"] == g.n * g.n  # connected graph
     for s in (0, 77_777, 99_999):
-        check_state(g, G, s)
+        check_state(g, G, s, **opts)
 
 
 def test_config_grid_sampled_sources():
     g = gg.config_graph("grid1000")
     G = bc.Graph(g)
     srcs = gg.config_sources("grid1000", g)[:16]
+    check_bc(g, G, srcs, **LAUNCH["grid1000"])  # the benchmark's launch settings
     check_bc(g, G, srcs)
     for s in srcs[:2]:
-        check_state(g, G, int(s))
+        check_state(g, G, int(s), **LAUNCH["grid1000"])
 
 
 @pytest.mark.slow
@@ -375,5 +379,5 @@ def test_config_rmat22_sampled_sources():
     g = gg.config_graph("rmat22")
     G = bc.Graph(g)
     srcs = gg.config_sources("rmat22", g)[:2]
-    check_bc(g, G, srcs)
-    check_state(g, G, int(srcs[0]))
+    check_bc(g, G, srcs, **LAUNCH["rmat22"])  # the benchmark's launch settings
+    check_state(g, G, int(srcs[0]), **LAUNCH["rmat22"])
