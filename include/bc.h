@@ -128,10 +128,12 @@ typedef struct {
     int32_t lds_vertices; /* batched: distances of this many highest in-degree vertices are
                              kept in LDS per source; 0 = as many as fit, -1 = none */
     int32_t dep_mode;     /* batched dependency pass: 0 = default (1), 1 = push along the
-                             shortest-path DAG recorded by the count pass (Kahn's order),
-                             2 = pull over out-arcs band by band in reverse */
+                             shortest-path DAG recorded by the count pass, band by band in
+                             reverse and in Kahn's order inside a band, 2 = pull over
+                             out-arcs band by band in reverse */
     int32_t virtual_warp; /* frontier expansion: 0 = by degree, one lane per vertex up to 8
-                             arcs, a group of 8 lanes up to 64, a whole wave above;
+                             arcs, a group of 8 lanes up to 64, a whole wave above (and in
+                             the batched form the whole workgroup above 512);
                              1, 2, 4, ..., 64 = a fixed group of that many lanes per vertex
                              (the warp-centric mapping of Sec. 3.4) */
     int32_t node_parallel;/* batched frontier expansion: 0 = over the queue (work-efficient,
