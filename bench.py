@@ -36,6 +36,9 @@ WORKLOADS = {
     "ablation": "thread-mapping variants on ER and Kronecker graphs n=2^14..2^18 (avg deg 32) "
                 "and n=2^17 (avg deg 4), degree sweeps on ER n=20000 and Kronecker 2^15 (avg deg 4..64), "
                 "w uniform [1,10], 256 sampled sources per graph",
+    "dynamic": "Barabasi-Albert n=100000 m=5, w uniform [1,1000]: a sequence of 8 seeded arc "
+               "changes (2 each of insert, delete, weight increase, weight decrease), each "
+               "applied to all-source BC with bc_update_arc_device",
     "serving": "8 resident graphs (ER n=10k/500k deg 8 w[1,100]; BA n=50k/1M m=5 w[1,1000]; "
                "grid 100x100/1414x1414 -2% w[1,255]; R-MAT scale 14/21 w[1,255]); Poisson "
                "arrivals; each request k-sampled BC, k log-uniform in [64,4096]",
@@ -123,6 +126,67 @@ def run_ablation(args):
         G.close()
     print(json.dumps({"metric": "thread-mapping ablation, weighted-BC GTEPS (batched form)",
                       "sources_per_graph": args.ablation_sources, "rows": rows}), flush=True)
+
+
+def run_dynamic(args):
+    """Dynamic updates on the BA workload: all-source BC is computed once, then
+    each arc change of a seeded sequence is applied with bc_update_arc_device
+    (only the affected sources run again, on the old and the new graph).  The
+    final centralities are checked against a full recompute of the final graph."""
+    import torch
+    from paper_1701_05975_amd import bc, graphgen as gg
+    from paper_1701_05975_amd.launch import LAUNCH
+
+    g = gg.config_graph("ba100k")
+    opts = bc.make_options(**LAUNCH["ba100k"])
+    n = g.n
+    G = bc.Graph(g)
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    cur = torch.empty(n, dtype=torch.float64, device="cuda")
+    bc.bc_compute_device(G.handle, src.data_ptr(), n, cur.data_ptr(), opts)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bc.bc_compute_device(G.handle, src.data_ptr(), n, cur.data_ptr(), opts)
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) * 1e3
+    print(f"# full all-source BC {full_ms:.1f} ms", file=sys.stderr, flush=True)
+    initial = cur.cpu().numpy()
+    rows = []
+    rng = np.random.default_rng(7)
+    for i, kind in enumerate(["insert", "delete", "increase", "decrease"] * 2):
+        change = gg.random_arc_change(g, kind, 1, 1000, seed=int(rng.integers(1 << 30)))
+        t0 = time.perf_counter()
+        g_new = gg.change_arc(g, *change)
+        Gn = bc.Graph(g_new)
+        t_build = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = bc.bc_update_arc_device(G.handle, Gn.handle, None, *change, cur.data_ptr(), 0, opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        row = {"change": kind, "arc": list(change), "affected_sources": k,
+               "update_ms": round(ms, 1), "graph_build_ms": round(t_build * 1e3, 1)}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        G.close()
+        g, G = g_new, Gn
+    full = torch.empty(n, dtype=torch.float64, device="cuda")
+    bc.bc_compute_device(G.handle, src.data_ptr(), n, full.data_ptr(), opts)
+    got, want = cur.cpu().numpy(), full.cpu().numpy()
+    # each update's rounding is relative to the centralities it started from
+    err = float(np.max(np.abs(got - want) /
+                       np.maximum(np.maximum(np.abs(want), np.abs(initial)), 1.0)))
+    mean_ms = float(np.mean([r["update_ms"] for r in rows]))
+    print(json.dumps({
+        "metric": "dynamic BC: ms per arc change (all-source BC kept current)",
+        "value": round(mean_ms, 1), "unit": "ms", "higher_is_better": False,
+        "median_ms": round(float(np.median([r["update_ms"] for r in rows])), 1),
+        "full_recompute_ms": round(full_ms, 1), "speedup_vs_full": round(full_ms / mean_ms, 2),
+        "mean_affected_fraction": round(float(np.mean([r["affected_sources"] for r in rows])) / n,
+                                        4),
+        "final_max_rel_dev_vs_full": err, "config": {"workload": WORKLOADS["dynamic"]},
+        "rows": rows}), flush=True)
+    assert err <= 1e-9, err
 
 
 def run_serving(args):
@@ -322,6 +386,9 @@ def main():
         return
     if args.config == "ablation":
         run_ablation(args)
+        return
+    if args.config == "dynamic":
+        run_dynamic(args)
         return
     import torch
 

@@ -237,6 +237,48 @@ bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t
                           uint64_t *sigma, double *delta);
 
 /*
+ * bc_update_arc_device -- centralities after one arc changes (dynamic BC, the
+ * extension Sec. 5 leaves to future work).
+ *
+ * The change: the arc tail -> head had weight w_old (0: absent) and has
+ * weight w_new (0: removed); w_old != w_new, both >= 0.  For an undirected
+ * graph the edge {tail, head} changes, i.e. both of its arcs.  g_old and
+ * g_new are the graph before and after (caller-created, same n and
+ * directedness, differing in that arc only: checked through n, directedness
+ * and nnz, otherwise the caller's responsibility).  g_rev is g_old with every
+ * arc reversed, for a directed graph; it must be NULL for an undirected one.
+ *
+ * bc_dev[n] (device) holds the centralities of g_old over all sources (as
+ * bc_compute_device with every vertex as a source) and receives those of
+ * g_new.  Only the affected sources are run again, once on each graph: a
+ * source s is affected when, with the distances before the change, the arc
+ * was on a shortest path from s (dist(s,tail) + w_old = dist(s,head)) or lies
+ * on or shortens one after it (dist(s,tail) + w_new <= dist(s,head)), for
+ * either arc of an undirected edge.  Every other source keeps its distances
+ * and shortest-path DAG, hence its dependencies.  dist(s, tail) and
+ * dist(s, head) come from two single-source passes on the reversed graph
+ * (g_rev, or g_old when undirected); a self-loop change affects no source.
+ * When more than half of the sources are affected, every source of g_new is
+ * run instead (n source passes rather than 2 x affected) and bc_dev is
+ * overwritten with that result.
+ *
+ * affected_dev (device int32[n], may be NULL) receives the affected sources
+ * in no particular order; *affected (may be NULL) their number.  Rounding:
+ * otherwise bc_dev[v] gains (sum after - sum before) over the affected
+ * sources, so its error is relative to the larger of the old and new
+ * centrality.  Runs on
+ * opt->stream (or the graphs' streams) and returns when bc_dev is complete.
+ *
+ * Errors: BC_E_INVAL (null graph or output, graphs that do not match, arc out
+ * of range, no change in weight, missing or superfluous g_rev), otherwise as
+ * bc_compute_device (bc_dev is then not valid).
+ */
+bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev,
+                               int32_t tail, int32_t head, int32_t w_old, int32_t w_new,
+                               const bc_options *opt, double *bc_dev, int32_t *affected_dev,
+                               int64_t *affected);
+
+/*
  * bc_algo_bytes -- the algorithmic HBM bytes of one source's Brandes pass:
  *   arcs * (16 + 2 * weight_bytes) + 72 * reached + 24 * dag_arcs + 20 * n
  * (two passes over the arcs of reached vertices with a 4-byte distance gather

@@ -9,6 +9,8 @@ from .oracle import (  # noqa: F401
     build,
     oracle_bc,
     oracle_bc_edges,
+    oracle_changed_sources,
+    oracle_source_changed,
     oracle_source_state,
     lib_path,
 )

@@ -134,3 +134,19 @@ def oracle_source_state(g, s: int, lib: str | None = None):
     if rc != 0:
         raise OracleError(f"oracle_source_state failed with code {rc}")
     return d, sigma, delta, int(nr.value)
+
+
+def oracle_source_changed(g_old, g_new, s: int, lib: str | None = None) -> bool:
+    """Whether the distances or shortest-path counts from s differ between two
+    graphs.  A change of the graph can alter the dependencies delta_s, and with
+    them the centralities, only through such a source."""
+    d0, s0, _, _ = oracle_source_state(g_old, s, lib)
+    d1, s1, _, _ = oracle_source_state(g_new, s, lib)
+    return not (np.array_equal(d0, d1) and np.array_equal(s0, s1))
+
+
+def oracle_changed_sources(g_old, g_new, lib: str | None = None) -> np.ndarray:
+    """Sorted vertices s for which oracle_source_changed holds (every vertex
+    tried: small graphs only)."""
+    return np.array([s for s in range(g_old.n) if oracle_source_changed(g_old, g_new, s, lib)],
+                    dtype=np.int32)

@@ -132,6 +132,8 @@ def _load():
         "bc_result_stats": ([P, ctypes.POINTER(bc_stats)], ctypes.c_int),
         "bc_destroy_result": ([P], ctypes.c_int),
         "bc_source_state": ([P, i32, ctypes.POINTER(bc_options), P, P, P], ctypes.c_int),
+        "bc_update_arc_device": ([P, P, P, i32, i32, i32, i32, ctypes.POINTER(bc_options), P,
+                                  P, ctypes.POINTER(i64)], ctypes.c_int),
         "bc_algo_bytes": ([i32, i32, i64, i64, i64], ctypes.c_double),
         "bc_server_create": ([ctypes.POINTER(bc_server_opts), ctypes.POINTER(P)], ctypes.c_int),
         "bc_server_submit": ([P, P, P, i64, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -277,6 +279,20 @@ def bc_source_state(g, s: int, n: int, options: bc_options | None = None):
     opt = ctypes.byref(options) if options is not None else None
     _check(_lib.bc_source_state(g, int(s), opt, _ptr(d), _ptr(sigma), _ptr(delta)))
     return d, sigma, delta
+
+
+def bc_update_arc_device(g_old, g_new, g_rev, tail: int, head: int, w_old: int, w_new: int,
+                         bc_dev_ptr: int, affected_dev_ptr: int = 0,
+                         options: bc_options | None = None) -> int:
+    """Updates bc_dev (all-source centralities of g_old) to those of g_new; returns
+    the number of sources run again (their ids go to affected_dev_ptr if given)."""
+    k = ctypes.c_int64(0)
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.bc_update_arc_device(g_old, g_new, g_rev, int(tail), int(head), int(w_old),
+                                     int(w_new), opt, ctypes.c_void_p(bc_dev_ptr),
+                                     ctypes.c_void_p(affected_dev_ptr or None),
+                                     ctypes.byref(k)))
+    return int(k.value)
 
 
 def bc_algo_bytes(n: int, weight_bytes: int, arcs: int, reached: int, dag_arcs: int) -> float:

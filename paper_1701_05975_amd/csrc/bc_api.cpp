@@ -1097,6 +1097,104 @@ bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t
     });
 }
 
+bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev,
+                               int32_t tail, int32_t head, int32_t w_old, int32_t w_new,
+                               const bc_options *opt, double *bc_dev, int32_t *affected_dev,
+                               int64_t *affected)
+{
+    return guarded([&] {
+        if (!g_old || !g_new || !bc_dev)
+            throw bc_error(BC_E_INVAL, "null argument");
+        const int32_t n = g_old->n;
+        if (g_new->n != n || g_new->directed != g_old->directed)
+            throw bc_error(BC_E_INVAL, "the two graphs differ in size or directedness");
+        if (tail < 0 || tail >= n || head < 0 || head >= n)
+            throw bc_error(BC_E_INVAL, "arc %d -> %d out of range", tail, head);
+        if (w_old < 0 || w_new < 0 || w_old == w_new)
+            throw bc_error(BC_E_INVAL, "weights %d -> %d are not a change", w_old, w_new);
+        if (g_old->directed) {
+            if (!g_rev || !g_rev->directed || g_rev->n != n || g_rev->nnz != g_old->nnz)
+                throw bc_error(BC_E_INVAL, "a directed graph needs its reverse (same n and nnz)");
+        } else if (g_rev) {
+            throw bc_error(BC_E_INVAL, "an undirected graph takes no reverse graph");
+        }
+        const int64_t per = g_old->directed ? 1 : 2;
+        const int64_t dn = per * ((w_new > 0 ? 1 : 0) - (w_old > 0 ? 1 : 0));
+        if (tail != head && g_new->nnz - g_old->nnz != dn)
+            throw bc_error(BC_E_INVAL, "arc counts %lld -> %lld do not match the change",
+                           (long long)g_old->nnz, (long long)g_new->nnz);
+        if (affected)
+            *affected = 0;
+        if (tail == head)
+            return; // a self-loop lies on no shortest path
+        // dist(s, tail) and dist(s, head) for every s: single-source passes from
+        // tail and head on the reversed graph (an undirected graph is its own)
+        bc_graph *gd = g_old->directed ? g_rev : g_old;
+        bc_options o;
+        memset(&o, 0, sizeof o);
+        if (opt)
+            o = *opt;
+        o.batch = 1;
+        o.autotune = 0;
+        const ResolvedOptions r = resolve_options(gd, &o, 1);
+        DevBuf dist, scratch, list, cnt;
+        dist.alloc((size_t)n * 8);
+        scratch.alloc((size_t)n * 8);
+        int32_t *dt = (int32_t *)dist.p, *dh = dt + n;
+        const int32_t ends[2] = {tail, head};
+        ensure_sources(gd, 1);
+        for (int i = 0; i < 2; ++i) {
+            hip_check(hipMemcpyAsync(gd->src_buf.p, &ends[i], 4, hipMemcpyHostToDevice,
+                                     r.stream),
+                      "upload endpoint");
+            compute_device(gd, (const int32_t *)gd->src_buf.p, &ends[i], 1, &o,
+                           (double *)scratch.p, nullptr);
+            Workspace &ws = r.mode == BC_MODE_PLAIN ? gd->plain : gd->batched;
+            hip_check(launch_export_state((char *)ws.base.p, ws.L, 0, n, i == 0 ? dt : dh,
+                                          nullptr, nullptr, gd->perm_dev(), r.stream),
+                      "export distances");
+        }
+        list.alloc((size_t)n * 4);
+        cnt.alloc(8);
+        hip_check(launch_fill_u32((uint32_t *)cnt.p, 1, 0u, r.stream), "clear count");
+        hip_check(launch_dynamic_affected(dt, dh, n, w_old, w_new, g_old->directed ? 0 : 1,
+                                          (int32_t *)list.p, (int *)cnt.p, r.stream),
+                  "affected sources");
+        int k = 0;
+        hip_check(hipMemcpyAsync(&k, cnt.p, 4, hipMemcpyDeviceToHost, r.stream), "count");
+        hip_check(hipStreamSynchronize(r.stream), "synchronize");
+        if (affected_dev && k > 0) {
+            hip_check(hipMemcpyAsync(affected_dev, list.p, (size_t)k * 4,
+                                     hipMemcpyDeviceToDevice, r.stream),
+                      "copy affected sources");
+            hip_check(hipStreamSynchronize(r.stream), "synchronize");
+        }
+        if (affected)
+            *affected = k;
+        if (k == 0)
+            return;
+        if (2 * (int64_t)k > (int64_t)n) {
+            // replacing k sources costs 2k source passes: more than running
+            // every source of the new graph once
+            const ResolvedOptions rn = resolve_options(g_new, opt, n);
+            hip_check(launch_iota((int32_t *)list.p, n, rn.stream), "source list");
+            compute_device(g_new, (const int32_t *)list.p, nullptr, n, opt, bc_dev, nullptr);
+            return;
+        }
+        // the affected sources' dependencies before and after the change
+        DevBuf before;
+        before.alloc((size_t)n * 8);
+        double *after = (double *)scratch.p;
+        compute_device(g_old, (const int32_t *)list.p, nullptr, k, opt, (double *)before.p,
+                       nullptr);
+        compute_device(g_new, (const int32_t *)list.p, nullptr, k, opt, after, nullptr);
+        const ResolvedOptions rn = resolve_options(g_new, opt, k);
+        hip_check(launch_dynamic_apply(bc_dev, (const double *)before.p, after, n, rn.stream),
+                  "apply");
+        hip_check(hipStreamSynchronize(rn.stream), "synchronize");
+    });
+}
+
 double bc_algo_bytes(int32_t n, int32_t weight_bytes, int64_t arcs, int64_t reached,
                      int64_t dag_arcs)
 {

@@ -82,5 +82,11 @@ hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, i
 hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, int n, int32_t *d,
                                uint64_t *sigma, double *delta, const int32_t *perm,
                                hipStream_t st);
+hipError_t launch_dynamic_affected(const int32_t *dt, const int32_t *dh, int n, int32_t w_old,
+                                   int32_t w_new, int both, int32_t *list, int *cnt,
+                                   hipStream_t st);
+hipError_t launch_iota(int32_t *list, int n, hipStream_t st);
+hipError_t launch_dynamic_apply(double *bc, const double *before, const double *after, int n,
+                                hipStream_t st);
 hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
                                     hipStream_t st);

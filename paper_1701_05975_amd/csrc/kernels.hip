@@ -901,9 +901,66 @@ __global__ void k_export_state(char *slab_base, SlabLayout L, int slot, int n, i
         const bool r = dv != BC_INF;
         const int32_t o = perm ? perm[v] : v;
         d[o] = (int32_t)dv;
-        sigma[o] = r ? S.sigma[v] : 0ull;
-        delta[o] = r ? S.delta[v] : 0.0;
+        if (sigma)
+            sigma[o] = r ? S.sigma[v] : 0ull;
+        if (delta)
+            delta[o] = r ? S.delta[v] : 0.0;
     }
+}
+
+// Dynamic update of one arc tail -> head, weight w_old -> w_new (0: absent).
+// With a = dist(s, tail) and b = dist(s, head) before the change, the arc is
+// in the shortest-path DAG of s before iff a + w_old = b, and it lies on, or
+// shortens, a shortest path after iff a + w_new <= b.  When neither holds the
+// old distances stay exact after the change and the set of tight arcs (the
+// DAG, hence the counts and dependencies of s) is the same.
+__device__ __forceinline__ bool arc_changes_dag(uint32_t a, uint32_t b, int32_t w_old,
+                                                int32_t w_new)
+{
+    if (a == BC_INF)
+        return false; // the tail is not reached from s
+    const uint64_t ta = a;
+    if (w_old > 0 && b != BC_INF && ta + (uint32_t)w_old == b)
+        return true;
+    return w_new > 0 && (b == BC_INF || ta + (uint32_t)w_new <= b);
+}
+
+// Sources whose DAG the change alters; dt[s] = dist(s, tail), dh[s] =
+// dist(s, head) in the caller's numbering (INT32_MAX: unreachable).  `both`:
+// the reverse arc head -> tail changes too (undirected graphs).
+__global__ void k_dynamic_affected(const int32_t *dt, const int32_t *dh, int n, int32_t w_old,
+                                   int32_t w_new, int both, int32_t *list, int *cnt)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of iterations (wave_alloc is a
+    // wave-wide operation)
+    const long long span = ((long long)n + stride - 1) / stride * stride;
+    for (long long s = blockIdx.x * blockDim.x + threadIdx.x; s < span; s += stride) {
+        bool hit = false;
+        if (s < n) {
+            const uint32_t a = (uint32_t)dt[s], b = (uint32_t)dh[s];
+            hit = arc_changes_dag(a, b, w_old, w_new) ||
+                  (both && arc_changes_dag(b, a, w_old, w_new));
+        }
+        const int k = wave_alloc(cnt, hit);
+        if (hit)
+            list[k] = (int32_t)s;
+    }
+}
+
+// list[i] = i (every vertex as a source)
+__global__ void k_iota(int32_t *list, int n)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        list[v] = v;
+}
+
+// bc += after - before, the affected sources' dependencies on the new graph
+// replacing those on the old one.
+__global__ void k_dynamic_apply(double *bc, const double *before, const double *after, int n)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        bc[v] += after[v] - before[v];
 }
 
 // Minimum outgoing weight per vertex (Delta_node of Sec. 3.2; INT32_MAX when
@@ -1107,5 +1164,34 @@ hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dno
     else
         hipLaunchKernelGGL(k_graph_vertex_info<false>, dim3(blocks), dim3(256), 0, st, g, dnode,
                            deg);
+    return hipGetLastError();
+}
+
+static int flat_blocks(int n)
+{
+    int blocks = (n + 255) / 256;
+    return blocks > 4096 ? 4096 : blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_dynamic_affected(const int32_t *dt, const int32_t *dh, int n, int32_t w_old,
+                                   int32_t w_new, int both, int32_t *list, int *cnt,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dynamic_affected, dim3(flat_blocks(n)), dim3(256), 0, st, dt, dh, n,
+                       w_old, w_new, both, list, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_dynamic_apply(double *bc, const double *before, const double *after, int n,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dynamic_apply, dim3(flat_blocks(n)), dim3(256), 0, st, bc, before,
+                       after, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *list, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_iota, dim3(flat_blocks(n)), dim3(256), 0, st, list, n);
     return hipGetLastError();
 }

@@ -287,6 +287,73 @@ def diamond_chain(k: int) -> CSRGraph:
 
 
 # --------------------------------------------------------------------------
+# Graph edits (inputs of the dynamic update)
+# --------------------------------------------------------------------------
+
+def _arcs(g: CSRGraph):
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    return src, g.col.astype(np.int64), g.w.astype(np.int64)
+
+
+def reversed_graph(g: CSRGraph) -> CSRGraph:
+    """Every arc (u, v, w) turned into (v, u, w)."""
+    src, dst, wt = _arcs(g)
+    return csr_from_arcs(g.n, dst, src, wt, directed=g.directed, m=g.m, name=g.name + "-rev")
+
+
+def change_arc(g: CSRGraph, tail: int, head: int, w_old: int, w_new: int) -> CSRGraph:
+    """g with one arc tail -> head of weight w_old (0: none) replaced by one of
+    weight w_new (0: none); for an undirected graph both arcs of the edge."""
+    src, dst, wt = _arcs(g)
+    pairs = [(tail, head)] if g.directed or tail == head else [(tail, head), (head, tail)]
+    keep = np.ones(src.shape[0], dtype=bool)
+    add_s, add_d, add_w = [], [], []
+    for a, b in pairs:
+        if w_old > 0:
+            hit = np.nonzero((src == a) & (dst == b) & (wt == w_old) & keep)[0]
+            if hit.shape[0] == 0:
+                raise ValueError(f"no arc {a} -> {b} of weight {w_old}")
+            keep[hit[0]] = False
+        if w_new > 0:
+            add_s.append(a)
+            add_d.append(b)
+            add_w.append(w_new)
+    src = np.concatenate([src[keep], np.asarray(add_s, np.int64)])
+    dst = np.concatenate([dst[keep], np.asarray(add_d, np.int64)])
+    wt = np.concatenate([wt[keep], np.asarray(add_w, np.int64)])
+    dm = (1 if w_new > 0 else 0) - (1 if w_old > 0 else 0)
+    return csr_from_arcs(g.n, src, dst, wt, directed=g.directed, m=g.m + dm, name=g.name)
+
+
+def random_arc_change(g: CSRGraph, kind: str, wlo: int, whi: int, seed: int):
+    """(tail, head, w_old, w_new) of one random change: 'insert' (a new arc
+    between two distinct vertices), 'delete', 'increase' or 'decrease' (an
+    existing arc, not a self-loop; a decrease needs a weight above 1)."""
+    rng = np.random.default_rng(seed)
+    src, dst, wt = _arcs(g)
+    if kind == "insert":
+        while True:
+            a, b = (int(x) for x in rng.integers(0, g.n, size=2))
+            if a != b:
+                return a, b, 0, int(rng.integers(wlo, whi + 1))
+    ok = src != dst
+    if kind == "decrease":
+        ok &= wt > 1
+    cand = np.nonzero(ok)[0]
+    if cand.shape[0] == 0:
+        raise ValueError(f"no arc for a {kind}")
+    e = int(cand[rng.integers(0, cand.shape[0])])
+    a, b, w = int(src[e]), int(dst[e]), int(wt[e])
+    if kind == "delete":
+        return a, b, w, 0
+    if kind == "increase":
+        return a, b, w, int(w + rng.integers(1, max(whi, 2) + 1))
+    if kind == "decrease":
+        return a, b, w, int(rng.integers(1, w))
+    raise ValueError(kind)
+
+
+# --------------------------------------------------------------------------
 # Benchmark configurations and source sampling
 # --------------------------------------------------------------------------
 

@@ -1,0 +1,142 @@
+"""Dynamic update of one arc on the GPU (bc_update_arc_device) against the
+oracle: the sources run again equal, exactly, the sources whose distances or
+path counts change, and the updated centralities equal the oracle's
+centralities of the changed graph.  Tolerance: the update adds (after -
+before) over the affected sources to the old value, so its rounding is
+relative to the larger of the old and new centrality: |got - want| <= 1e-9
+(|want| + |old|)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1701_05975_amd import bc, graphgen as gg
+from paper_1701_05975_amd.launch import LAUNCH
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["insert", "delete", "increase", "decrease"]
+GRAPHS = [
+    gg.random_graph(300, 0.02, 1, 4, seed=21),                  # undirected, ties
+    gg.random_graph(300, 0.015, 1, 9, seed=22, directed=True),
+    gg.ba_graph(1500, 3, 1, 30, seed=23),                       # renumbered on the device
+    gg.rmat_graph(10, 8 << 10, .57, .19, .19, 1, 9, seed=24),   # directed, renumbered
+    gg.grid_graph(25, 25, 40, 1, 9, seed=25),
+]
+
+
+def run_update(g, change, keep_order=False, **opts):
+    g_new = gg.change_arc(g, *change)
+    Go = bc.Graph(g, keep_order=keep_order)
+    Gn = bc.Graph(g_new, keep_order=keep_order)
+    Gr = bc.Graph(gg.reversed_graph(g), keep_order=keep_order) if g.directed else None
+    n = g.n
+    o = bc.make_options(**opts)
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    cur = torch.empty(n, dtype=torch.float64, device="cuda")
+    bc.bc_compute_device(Go.handle, src.data_ptr(), n, cur.data_ptr(), o)
+    old = cur.cpu().numpy().copy()
+    aff = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    k = bc.bc_update_arc_device(Go.handle, Gn.handle, Gr.handle if Gr else None, *change,
+                                cur.data_ptr(), aff.data_ptr(), o)
+    torch.cuda.synchronize()
+    got = cur.cpu().numpy()
+    affected = np.sort(aff[:k].cpu().numpy())
+    return g_new, old, got, affected, (Go, Gn, Gr)
+
+
+def assert_update_close(got, want, old, tol=1e-9):
+    err = np.abs(got - want)
+    bound = tol * (np.abs(want) + np.abs(old))
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]], old[bad[:5]])
+
+
+def cases():
+    for gi, g in enumerate(GRAPHS):
+        for ki, kind in enumerate(KINDS):
+            yield pytest.param(g, kind, 1000 + 10 * gi + ki, id=f"{g.name or gi}-{kind}")
+
+
+@pytest.mark.parametrize("g,kind,seed", list(cases()))
+def test_update_matches_oracle(g, kind, seed):
+    change = gg.random_arc_change(g, kind, 1, 9, seed=seed)
+    print(f"graph {g.name} n={g.n} change {change}", flush=True)
+    g_new, old, got, affected, _ = run_update(g, change)
+    assert np.array_equal(affected, oracle.oracle_changed_sources(g, g_new))
+    assert_update_close(got, oracle.oracle_bc(g_new, np.arange(g.n)), old)
+
+
+@pytest.mark.parametrize("opts", [dict(keep_order=True), dict(mode=bc.BC_MODE_PLAIN),
+                                  dict(accumulate=2, wg_threads=256, batch=7)],
+                         ids=["keep_order", "plain", "atomic"])
+def test_update_options(opts):
+    opts = dict(opts)
+    keep = opts.pop("keep_order", False)
+    for g in (GRAPHS[2], GRAPHS[3]):
+        change = gg.random_arc_change(g, "insert", 1, 9, seed=77)
+        g_new, old, got, affected, _ = run_update(g, change, keep_order=keep, **opts)
+        assert np.array_equal(affected, oracle.oracle_changed_sources(g, g_new))
+        assert_update_close(got, oracle.oracle_bc(g_new, np.arange(g.n)), old)
+
+
+def test_update_edge_cases():
+    # a self-loop lies on no shortest path: nothing is run again
+    g = gg.cycle_graph(8, 2)
+    g_new, old, got, affected, _ = run_update(g, (3, 3, 0, 1))
+    assert affected.size == 0 and np.array_equal(got, old)
+    # an arc into an unreachable part makes it reachable (directed)
+    g = gg.csr_from_arcs(6, [0, 1, 3, 4], [1, 2, 4, 5], [1, 1, 1, 1], directed=True)
+    g_new, old, got, affected, _ = run_update(g, (2, 3, 0, 4))
+    assert np.array_equal(affected, oracle.oracle_changed_sources(g, g_new))
+    assert_update_close(got, oracle.oracle_bc(g_new, np.arange(g.n)), old)
+    # removing a bridge disconnects; weights that tie after the change
+    g = gg.path_graph(7, [1, 2, 3, 4, 5, 6])
+    for change in [(2, 3, 3, 0), (0, 2, 0, 3), (4, 5, 5, 1)]:
+        g_new, old, got, affected, _ = run_update(g, change)
+        assert np.array_equal(affected, oracle.oracle_changed_sources(g, g_new))
+        assert_update_close(got, oracle.oracle_bc(g_new, np.arange(g.n)), old)
+
+
+def test_update_rejects_bad_arguments():
+    g = GRAPHS[0]
+    Go = bc.Graph(g)
+    Gn = bc.Graph(gg.change_arc(g, 0, 1, 0, 3))
+    cur = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+
+    def st(*a):
+        with pytest.raises(bc.BCError) as ei:
+            bc.bc_update_arc_device(*a)
+        return ei.value.status
+
+    assert st(Go.handle, Gn.handle, None, 0, 1, 0, 0, cur.data_ptr()) == bc.BC_E_INVAL
+    assert st(Go.handle, Gn.handle, None, 0, g.n, 0, 3, cur.data_ptr()) == bc.BC_E_INVAL
+    assert st(Go.handle, Gn.handle, None, 0, 1, 0, 3, 0) == bc.BC_E_INVAL
+    assert st(Go.handle, Go.handle, None, 0, 1, 0, 3, cur.data_ptr()) == bc.BC_E_INVAL  # nnz
+    assert st(Go.handle, Gn.handle, Go.handle, 0, 1, 0, 3, cur.data_ptr()) == bc.BC_E_INVAL
+    d = GRAPHS[1]
+    Do = bc.Graph(d)
+    Dn = bc.Graph(gg.change_arc(d, 0, 1, 0, 3))
+    assert st(Do.handle, Dn.handle, None, 0, 1, 0, 3, cur.data_ptr()) == bc.BC_E_INVAL
+
+
+def test_update_full_size_ba100k():
+    """BA, n = 100,000: the update equals a full recompute of the changed graph
+    (the full recompute itself is checked against the oracle in the parity
+    suite), and for 32 sampled sources membership in the affected set equals
+    the oracle's changed-source test."""
+    g = gg.config_graph("ba100k")
+    opts = LAUNCH["ba100k"]
+    rng = np.random.default_rng(5)
+    for kind in ("insert", "delete"):
+        change = gg.random_arc_change(g, kind, 1, 1000, seed=int(rng.integers(1 << 30)))
+        print(f"ba100k change {change}", flush=True)
+        g_new, old, got, affected, (Go, Gn, Gr) = run_update(g, change, **opts)
+        full, _ = Gn.bc(None, **opts)
+        assert_update_close(got, full, old)
+        members = set(affected.tolist())
+        for s in rng.choice(g.n, size=32, replace=False):
+            assert (int(s) in members) == oracle.oracle_source_changed(g, g_new, int(s)), s
+        print(f"  affected {affected.size} of {g.n}", flush=True)
