@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (16, 32)")
     ap.add_argument("--edges", action="store_true",
                     help="time node + edge betweenness (bc_compute_edges_device)")
+    ap.add_argument("--interleaved-sources", type=int, default=256,
+                    help="sources timed in the source-interleaved form (0: skip)")
     ap.add_argument("--ablation-sources", type=int, default=256)
     ap.add_argument("--variants", default="", help="ablation: comma-separated name parts to run")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
@@ -477,6 +479,23 @@ def main():
                  "sources": int(len(ps)), "ms": round(tp * 1e3, 2),
                  "batched_over_plain": round(gteps / (len(ps) * g.m / tp / 1e9), 2)}
 
+    interleaved = None
+    if args.interleaved_sources > 0 and not args.edges:
+        # the source-interleaved form (64 sources per wave) on the first sources
+        isrc = sources[: min(args.interleaved_sources, k)]
+        i_dev = torch.from_numpy(np.ascontiguousarray(isrc)).to("cuda")
+        io = bc.make_options(mode=bc.BC_MODE_INTERLEAVED, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        ti0 = time.perf_counter()
+        ist = bc.bc_compute_device(G.handle, i_dev.data_ptr(), len(isrc), out.data_ptr(), io)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - ti0
+        iv = len(isrc) * g.m / ti / 1e9
+        interleaved = {"value": round(iv, 6), "unit": "GTEPS", "sources": int(len(isrc)),
+                       "ms": round(ti * 1e3, 2), "delta": ist.delta, "rounds": ist.iterations,
+                       "bands": ist.bands, "batched_over_interleaved": round(gteps / iv, 2)}
+        print(f"# interleaved: {json.dumps(interleaved)}", file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu else cpu_baseline(g, sources, args.cpu_sources)
 
     rec = {
@@ -510,6 +529,7 @@ def main():
         },
         "roofline": roofline,
         "plain": plain,
+        "interleaved": interleaved,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

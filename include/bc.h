@@ -106,7 +106,14 @@ typedef enum {
     BC_MODE_AUTO = 0,    /* batched */
     BC_MODE_BATCHED = 1, /* many sources in flight, one workgroup and one state slab per source,
                             one persistent launch (coarse-grained source parallelism, Sec. 3.1) */
-    BC_MODE_PLAIN = 2    /* one source at a time on the whole GPU, phase by phase */
+    BC_MODE_PLAIN = 2,   /* one source at a time on the whole GPU, phase by phase */
+    BC_MODE_INTERLEAVED = 3 /* sources in groups of 64 sharing one wavefront, one lane per
+                               source, the state of a group laid out [vertex][source] so that
+                               an arc read serves all 64 sources; rounds over queues of
+                               (group, vertex) entries, as many groups per sweep as 60% of the
+                               free device memory (at most 96 GiB) holds, or batch
+                               sources (rounded up to a multiple of 64) when batch > 0;
+                               lane and workgroup options do not apply */
 } bc_mode;
 
 /*
@@ -116,7 +123,8 @@ typedef enum {
  */
 typedef struct {
     int32_t mode;         /* bc_mode */
-    int32_t batch;        /* batched: sources in flight (state slabs); 0 = fill the GPU */
+    int32_t batch;        /* batched: sources in flight (state slabs); 0 = fill the GPU;
+                             interleaved: at most this many sources per sweep */
     int32_t delta;        /* near-far band width in weight units (>= 1); 0 = heuristic */
     int32_t lane_max_deg; /* count and dependency passes: vertices with at most this many
                              in-arcs (recorded predecessors) are handled by one lane, larger

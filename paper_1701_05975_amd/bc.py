@@ -36,7 +36,7 @@ STATUS_NAMES = {
 BC_DIRECTED = 1
 BC_KEEP_ORDER = 2
 BC_EDGE_BC = 4
-BC_MODE_AUTO, BC_MODE_BATCHED, BC_MODE_PLAIN = 0, 1, 2
+BC_MODE_AUTO, BC_MODE_BATCHED, BC_MODE_PLAIN, BC_MODE_INTERLEAVED = 0, 1, 2, 3
 
 INT32_MAX = 2**31 - 1
 

@@ -564,7 +564,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     memset(&o, 0, sizeof o);
     if (opt)
         o = *opt;
-    if (o.mode < 0 || o.mode > BC_MODE_PLAIN)
+    if (o.mode < 0 || o.mode > BC_MODE_INTERLEAVED)
         throw bc_error(BC_E_INVAL, "unknown mode %d", o.mode);
     if (o.batch < 0 || o.delta < 0 || o.lane_max_deg < 0 || o.wg_threads < 0 ||
         o.lds_vertices < -1)
@@ -579,7 +579,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "lds_bits must be 0, 16 or 32");
     if (o.node_parallel < 0 || o.node_parallel > 1)
         throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
-    r.mode = o.mode == BC_MODE_PLAIN ? BC_MODE_PLAIN : BC_MODE_BATCHED;
+    r.mode = o.mode == BC_MODE_PLAIN || o.mode == BC_MODE_INTERLEAVED ? o.mode : BC_MODE_BATCHED;
     r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
     r.wg_threads = o.wg_threads ? o.wg_threads : 256;
     if (r.wg_threads != 256 && r.wg_threads != 512 && r.wg_threads != 1024)
@@ -590,6 +590,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.dep_mode = o.dep_mode ? o.dep_mode : 1;
     r.vw = o.virtual_warp;
     r.node_parallel = o.node_parallel;
+    r.il_groups = (int)std::min<int64_t>(((int64_t)o.batch + 63) / 64, INT32_MAX);
     int per_cu = 1;
     r.lds_bits = lds_bits_for(g, o.lds_bits);
     batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_bits,
@@ -615,7 +616,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
 // ---------------------------------------------------------------------------
 // Drivers
 // ---------------------------------------------------------------------------
-static void reset_counters(bc_graph *g, hipStream_t st)
+void reset_device_counters(bc_graph *g, hipStream_t st)
 {
     DevCounters *c = (DevCounters *)g->ctl.p;
     hip_check(launch_fill_u64((unsigned long long *)c, sizeof(DevCounters) / 8, 0ull, st),
@@ -623,7 +624,7 @@ static void reset_counters(bc_graph *g, hipStream_t st)
     hip_check(launch_fill_u64(&c->err[1], 1, (unsigned long long)INT64_MAX, st), "reset");
 }
 
-static void read_counters(bc_graph *g, hipStream_t st, DevCounters &out)
+void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out)
 {
     hip_check(hipMemcpyAsync(g->host_counters, g->ctl.p, sizeof(DevCounters),
                              hipMemcpyDeviceToHost, st),
@@ -687,7 +688,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
 {
     hipStream_t st = r.stream;
     ensure_slabs(g, g->batched, r.batch, st);
-    reset_counters(g, st);
+    reset_device_counters(g, st);
     const bool atomic_bc = r.accumulate == 2;
     if (atomic_bc || k == 0)
         hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
@@ -734,7 +735,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
                       "reduce");
     }
     hip_check(hipEventRecord(e1, st), "event");
-    read_counters(g, st, cnt);
+    read_device_counters(g, st, cnt);
     hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
     if (kernel_ms) {
         *kernel_ms = 0.f;
@@ -750,7 +751,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
 {
     hipStream_t st = r.stream;
     ensure_slabs(g, g->plain, 1, st);
-    reset_counters(g, st);
+    reset_device_counters(g, st);
     hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)g->n, 0ull, st), "zero");
     PlainArgs a;
     a.g = g->view();
@@ -832,7 +833,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
             hip_check(launch_plain_clear_infar(a, st), "clear");
     }
     hip_check(hipEventRecord(e1, st), "event");
-    read_counters(g, st, cnt);
+    read_device_counters(g, st, cnt);
     hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -846,7 +847,7 @@ void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host
         // edge betweenness comes from the recorded-DAG dependency pass
         if (!g->edges_ready)
             throw bc_error(BC_E_INVAL, "the graph was created without BC_EDGE_BC");
-        if (r.mode == BC_MODE_PLAIN)
+        if (r.mode != BC_MODE_BATCHED)
             throw bc_error(BC_E_INVAL, "edge betweenness needs the batched form");
         r.dep_mode = 1;
         r.autotune = 0;
@@ -870,6 +871,10 @@ void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host
             src_host = hs.data();
         }
         run_plain(g, r, src_host, k, bc_dev, cnt, ms);
+        kms = ms;
+        launches = 0;
+    } else if (r.mode == BC_MODE_INTERLEAVED) {
+        run_interleaved(g, r, src_dev, k, bc_dev, cnt, ms);
         kms = ms;
         launches = 0;
     } else {
@@ -1074,6 +1079,8 @@ bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t
             o = *opt;
         o.batch = 1;
         o.autotune = 0;
+        if (o.mode == BC_MODE_INTERLEAVED)
+            throw bc_error(BC_E_INVAL, "per-source state comes from the batched or plain form");
         ResolvedOptions r = resolve_options(g, &o, 1);
         ensure_sources(g, 1);
         hip_check(hipMemcpyAsync(g->src_buf.p, &s, 4, hipMemcpyHostToDevice, r.stream), "src");
@@ -1136,6 +1143,8 @@ bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev
             o = *opt;
         o.batch = 1;
         o.autotune = 0;
+        if (o.mode == BC_MODE_INTERLEAVED)
+            o.mode = BC_MODE_BATCHED; // the endpoint distances come from a per-source slab
         const ResolvedOptions r = resolve_options(gd, &o, 1);
         DevBuf dist, scratch, list, cnt;
         dist.alloc((size_t)n * 8);

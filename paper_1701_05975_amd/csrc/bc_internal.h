@@ -55,6 +55,7 @@ struct ResolvedOptions {
     int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
     int vw = 0;           // expansion lanes per vertex (0 adaptive)
     int node_parallel = 0;
+    int il_groups = 0;    // interleaved form: groups of 64 sources per sweep (0 = by memory)
     hipStream_t stream = nullptr;
 };
 
@@ -132,6 +133,13 @@ void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host
                     double *ebc_dev = nullptr);
 void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int32_t *src_dev,
               int64_t k);
+void reset_device_counters(bc_graph *g, hipStream_t st);
+void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);
+// Source-interleaved form: groups of 64 sources per sweep for n vertices, k
+// sources and the given free device bytes (0: not even one group fits).
+int interleaved_groups_per_sweep(int32_t n, int64_t k, size_t free_bytes);
+void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
+                     double *bc_dev, DevCounters &cnt, float &ms);
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
                  double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms,
                  double *ebc_dev = nullptr);

@@ -1,0 +1,475 @@
+// interleaved.hip -- source-interleaved multi-source form of Brandes' method.
+//
+// A group of 64 sources shares one wavefront, one lane per source.  The state
+// of a group is laid out vertex-major with the 64 sources of a vertex side by
+// side ([group][vertex][lane]): when a wave walks the arcs of a vertex, every
+// arc is read once for all 64 sources, and the distance, count and dependency
+// accesses of the wave at the arc's head are one contiguous row (256 bytes of
+// distances, 512 of counts or dependencies) instead of 64 scattered lines.
+//
+// Per group the passes are those of the other forms (Sec. 2.1, Algs. 1-3):
+//   forward  -- near-far bands of width Delta shared by the 64 sources
+//               (Sec. 3.2): a vertex is queued once per round with the mask of
+//               the sources whose distance at it improved below the band
+//               threshold; improvements beyond it go to a far list with a
+//               per-vertex mask and return when the threshold passes them;
+//   counts   -- sigma in topological order of each source's shortest-path
+//               DAG: every vertex counts its tight in-arcs per source, the
+//               sources start, and a vertex whose count reaches zero for a
+//               source has its final sigma and pushes it along its tight
+//               out-arcs (Alg. 2's counting rule, in Kahn's order);
+//   deps     -- the same in reverse: tight out-arcs counted, the DAG's leaves
+//               start, and a final vertex pushes sigma_u/sigma_w (1 + delta_w)
+//               into its tight predecessors (Alg. 3);
+//   BC       -- each vertex adds its dependencies over the lanes whose source
+//               is another vertex (Alg. 3), in a fixed order.
+// Every round is one launch over a queue of (group, vertex) entries; the host
+// reads the queue lengths between launches.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace {
+
+__device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return (unsigned long long)hi << 32 | lo;
+}
+
+__device__ __forceinline__ size_t cell(uint32_t e, int lane)
+{
+    return (size_t)e * WAVE + (size_t)lane;
+}
+
+// Appends entry e to a queue unless this round already queued it.
+__device__ __forceinline__ void queue_once(const IlArgs &a, uint32_t e, uint32_t round,
+                                           uint32_t *qout, unsigned int *qlen)
+{
+    if (atomicExch(&a.stamp[e], round) != round)
+        qout[atomicAdd(qlen, 1u)] = e;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32_il(uint32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(x, o);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__global__ void k_il_init(IlArgs a)
+{
+    const size_t cells = (size_t)a.groups * (size_t)a.n * WAVE;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        a.d[i] = BC_INF;
+        a.sigma[i] = 0ull;
+        a.delta[i] = 0.0;
+        a.cnt[i] = 0;
+    }
+    const size_t entries = (size_t)a.groups * (size_t)a.n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += stride) {
+        a.act[i] = 0ull;
+        a.far[i] = 0ull;
+        a.stamp[i] = 0u;
+    }
+}
+
+// Lane j of the sweep takes source-list entry j (none past k): distance 0,
+// one path, queued with its lane bit.
+__global__ void k_il_seed(IlArgs a, const int32_t *sources, long long k, const int32_t *iperm,
+                          uint32_t *qout, uint32_t round)
+{
+    const int lanes = a.groups * WAVE;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < lanes; j += gridDim.x * blockDim.x) {
+        int32_t s = -1;
+        if (j < k) {
+            const int32_t s_in = sources[j];
+            if (s_in < 0 || s_in >= a.n)
+                atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_SOURCE);
+            else
+                s = iperm ? iperm[s_in] : s_in;
+        }
+        a.lane_src[j] = s;
+        if (s < 0)
+            continue;
+        const uint32_t e = (uint32_t)(j / WAVE) * (uint32_t)a.n + (uint32_t)s;
+        const int lane = j % WAVE;
+        a.d[cell(e, lane)] = 0u;
+        a.sigma[cell(e, lane)] = 1ull;
+        atomicOr(&a.act[e], 1ull << lane);
+        queue_once(a, e, round, qout, &a.ctl->qlen);
+    }
+}
+
+// One forward round: each queued vertex relaxes its out-arcs for the lanes in
+// its mask whose distance lies below the band threshold.
+template <bool PACKED>
+__global__ void k_il_relax(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
+                           uint32_t *fout, uint32_t thr, uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const DevGraph &g = a.g;
+    for (uint32_t i = wid; i < qlen; i += nw) {
+        const uint32_t e = q[i];
+        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
+        unsigned long long m = 0;
+        if (lane == 0)
+            m = atomicExch(&a.act[e], 0ull);
+        m = first_lane_u64(m);
+        if (m == 0)
+            continue;
+        const bool on = (m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
+        const bool live = on && dv < thr;
+        const uint32_t base = grp * (uint32_t)a.n;
+        const uint32_t beg = g.row[v], end = g.row[v + 1];
+        for (uint32_t j = beg; j < end; ++j) {
+            uint32_t u, w;
+            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
+            const uint32_t eu = base + u;
+            bool imp = false;
+            uint32_t nd = 0;
+            if (live) {
+                nd = dv + w;
+                imp = nd < atomicMin(&a.d[cell(eu, lane)], nd);
+            }
+            const unsigned long long bn = __ballot(imp && nd < thr);
+            const unsigned long long bf = __ballot(imp && nd >= thr);
+            if (lane == 0) {
+                if (bn) {
+                    atomicOr(&a.act[eu], bn);
+                    queue_once(a, eu, round, qout, &a.ctl->qlen);
+                }
+                if (bf && atomicOr(&a.far[eu], bf) == 0ull)
+                    fout[atomicAdd(&a.ctl->flen, 1u)] = eu;
+            }
+        }
+    }
+}
+
+// Far-list pass when the band threshold moves from thr_old to thr_new: lanes
+// already below thr_old are settled (dropped), lanes below thr_new join the
+// next band, the others stay (with their least distance reported).
+__global__ void k_il_far(IlArgs a, const uint32_t *fin, uint32_t flen, uint32_t *qout,
+                         uint32_t *fout, uint32_t thr_old, uint32_t thr_new, uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    for (uint32_t i = wid; i < flen; i += nw) {
+        const uint32_t e = fin[i];
+        const unsigned long long fm = first_lane_u64(lane == 0 ? a.far[e] : 0ull);
+        const bool on = (fm >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
+        const bool drop = on && dv < thr_old;
+        const bool move = on && !drop && dv < thr_new;
+        const bool keep = on && !drop && !move;
+        const unsigned long long km = __ballot(keep), mv = __ballot(move);
+        const uint32_t kmin = wave_min_u32_il(keep ? dv : BC_INF);
+        if (lane == 0) {
+            a.far[e] = km;
+            if (mv) {
+                atomicOr(&a.act[e], mv);
+                queue_once(a, e, round, qout, &a.ctl->qlen);
+            }
+            if (km) {
+                fout[atomicAdd(&a.ctl->flen, 1u)] = e;
+                atomicMin(&a.ctl->minkept, kmin);
+            }
+        }
+    }
+}
+
+// Tight in-arcs per (vertex, source): the number of DAG predecessors whose
+// counts must arrive before the vertex's count is final.  The sources (the
+// only reached vertices without one) are queued.
+template <bool PACKED>
+__global__ void k_il_count_in(IlArgs a, uint32_t *qout, uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t entries = (uint32_t)a.groups * (uint32_t)a.n;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const DevGraph &g = a.g;
+    for (uint32_t e = wid; e < entries; e += nw) {
+        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
+        const uint32_t dv = a.d[cell(e, lane)];
+        const bool reached = dv != BC_INF;
+        if (__ballot(reached) == 0ull)
+            continue;
+        const uint32_t base = grp * (uint32_t)a.n;
+        int32_t c = 0;
+        for (uint32_t j = g.trow[v]; j < g.trow[v + 1]; ++j) {
+            uint32_t p, w;
+            arc_at<PACKED>(g.tarc, g.twt, j, g.wshift, g.wmask, p, w);
+            if (reached) {
+                const uint32_t dp = a.d[cell(base + p, lane)];
+                c += (dp != BC_INF && (uint64_t)dp + w == dv) ? 1 : 0;
+            }
+        }
+        a.cnt[cell(e, lane)] = c;
+        const unsigned long long ready = __ballot(reached && c == 0);
+        const unsigned long long nr = __ballot(reached);
+        if (lane == 0) {
+            atomicAdd(&a.ctl->reached, (unsigned long long)__popcll(nr));
+            if (ready) {
+                a.act[e] = ready;
+                queue_once(a, e, round, qout, &a.ctl->qlen);
+            }
+        }
+    }
+}
+
+// One count round: vertices whose count is final for the lanes in their mask
+// add it into their tight out-neighbours; a neighbour whose last pending
+// predecessor this was becomes final for that lane and is queued.
+template <bool PACKED>
+__global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
+                           uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const DevGraph &g = a.g;
+    for (uint32_t i = wid; i < qlen; i += nw) {
+        const uint32_t e = q[i];
+        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
+        unsigned long long m = 0;
+        if (lane == 0)
+            m = atomicExch(&a.act[e], 0ull);
+        m = first_lane_u64(m);
+        if (m == 0)
+            continue;
+        const bool on = (m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
+        const unsigned long long sv = on ? a.sigma[cell(e, lane)] : 0ull;
+        const uint32_t base = grp * (uint32_t)a.n;
+        bool ovf = false;
+        for (uint32_t j = g.row[v]; j < g.row[v + 1]; ++j) {
+            uint32_t u, w;
+            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
+            const uint32_t eu = base + u;
+            bool ready = false;
+            const uint32_t du = on ? a.d[cell(eu, lane)] : BC_INF;
+            if (du != BC_INF && du == (uint64_t)dv + w) {
+                const unsigned long long old = atomicAdd(&a.sigma[cell(eu, lane)], sv);
+                ovf |= old + sv < old;
+                ready = atomicSub(&a.cnt[cell(eu, lane)], 1) == 1;
+            }
+            const unsigned long long br = __ballot(ready);
+            if (lane == 0 && br) {
+                atomicOr(&a.act[eu], br);
+                queue_once(a, eu, round, qout, &a.ctl->qlen);
+            }
+        }
+        if (ovf) {
+            atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_SIGMA);
+            atomicMin(&a.err[1], (unsigned long long)(a.src_base + (long long)grp * WAVE + lane));
+        }
+    }
+}
+
+// Tight out-arcs per (vertex, source): the DAG successors whose dependencies
+// must arrive first.  The reached vertices without one (the DAG's leaves) are
+// queued.
+template <bool PACKED>
+__global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t entries = (uint32_t)a.groups * (uint32_t)a.n;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const DevGraph &g = a.g;
+    for (uint32_t e = wid; e < entries; e += nw) {
+        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
+        const uint32_t dv = a.d[cell(e, lane)];
+        const bool reached = dv != BC_INF;
+        if (__ballot(reached) == 0ull)
+            continue;
+        const uint32_t base = grp * (uint32_t)a.n;
+        int32_t c = 0;
+        for (uint32_t j = g.row[v]; j < g.row[v + 1]; ++j) {
+            uint32_t u, w;
+            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
+            if (reached) {
+                const uint32_t du = a.d[cell(base + u, lane)];
+                c += (du != BC_INF && du == (uint64_t)dv + w) ? 1 : 0;
+            }
+        }
+        a.cnt[cell(e, lane)] = c;
+        const unsigned long long leaves = __ballot(reached && c == 0);
+        if (lane == 0 && leaves) {
+            a.act[e] = leaves;
+            queue_once(a, e, round, qout, &a.ctl->qlen);
+        }
+    }
+}
+
+// One dependency round: vertices whose dependency is final for the lanes in
+// their mask push sigma_p / sigma_v (1 + delta_v) into each tight predecessor
+// p; a predecessor whose last pending successor this was is queued.
+template <bool PACKED>
+__global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
+                           uint32_t round)
+{
+    const int lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const DevGraph &g = a.g;
+    for (uint32_t i = wid; i < qlen; i += nw) {
+        const uint32_t e = q[i];
+        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
+        unsigned long long m = 0;
+        if (lane == 0)
+            m = atomicExch(&a.act[e], 0ull);
+        m = first_lane_u64(m);
+        if (m == 0)
+            continue;
+        const bool on = (m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
+        const double sv = on ? (double)a.sigma[cell(e, lane)] : 1.0;
+        const double f = on ? 1.0 + a.delta[cell(e, lane)] : 0.0;
+        const uint32_t base = grp * (uint32_t)a.n;
+        for (uint32_t j = g.trow[v]; j < g.trow[v + 1]; ++j) {
+            uint32_t p, w;
+            arc_at<PACKED>(g.tarc, g.twt, j, g.wshift, g.wmask, p, w);
+            const uint32_t ep = base + p;
+            bool ready = false;
+            if (on) {
+                const uint32_t dp = a.d[cell(ep, lane)];
+                if (dp != BC_INF && (uint64_t)dp + w == dv) {
+                    const double sp = (double)a.sigma[cell(ep, lane)];
+                    atomicAdd(&a.delta[cell(ep, lane)], sp / sv * f);
+                    ready = atomicSub(&a.cnt[cell(ep, lane)], 1) == 1;
+                }
+            }
+            const unsigned long long br = __ballot(ready);
+            if (lane == 0 && br) {
+                atomicOr(&a.act[ep], br);
+                queue_once(a, ep, round, qout, &a.ctl->qlen);
+            }
+        }
+    }
+}
+
+// bc[v] += the dependencies of v over every lane of every group whose source
+// is another vertex; one wave per vertex, groups in order, lanes summed by a
+// fixed tree.
+__global__ void k_il_bc(IlArgs a, double *bc, const int32_t *perm)
+{
+    const int lane = lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    for (uint32_t v = wid; v < (uint32_t)a.n; v += nw) {
+        double acc = 0.0;
+        for (int grp = 0; grp < a.groups; ++grp) {
+            const int32_t s = a.lane_src[grp * WAVE + lane];
+            const uint32_t e = (uint32_t)grp * (uint32_t)a.n + v;
+            if (s >= 0 && (uint32_t)s != v)
+                acc += a.delta[cell(e, lane)];
+        }
+        acc = wave_sum_f64(acc);
+        if (lane == 0)
+            bc[perm ? perm[v] : (int32_t)v] += acc;
+    }
+}
+
+int wave_blocks(size_t waves)
+{
+    // 256-thread blocks (4 waves each)
+    size_t b = (waves + 3) / 4;
+    if (b > 16384)
+        b = 16384;
+    return b < 1 ? 1 : (int)b;
+}
+
+} // namespace
+
+hipError_t launch_il_init(const IlArgs &a, const int32_t *sources, long long k,
+                          const int32_t *iperm, uint32_t *qout, uint32_t round, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_il_init, dim3(8192), dim3(256), 0, st, a);
+    const int lanes = a.groups * WAVE;
+    hipLaunchKernelGGL(k_il_seed, dim3((lanes + 255) / 256), dim3(256), 0, st, a, sources, k,
+                       iperm, qout, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_il_relax(const IlArgs &a, bool packed, const uint32_t *q, uint32_t qlen,
+                           uint32_t *qout, uint32_t *fout, uint32_t thr, uint32_t round,
+                           hipStream_t st)
+{
+    const dim3 grid(wave_blocks(qlen)), block(256);
+    if (packed)
+        hipLaunchKernelGGL(k_il_relax<true>, grid, block, 0, st, a, q, qlen, qout, fout, thr,
+                           round);
+    else
+        hipLaunchKernelGGL(k_il_relax<false>, grid, block, 0, st, a, q, qlen, qout, fout, thr,
+                           round);
+    return hipGetLastError();
+}
+
+hipError_t launch_il_far(const IlArgs &a, const uint32_t *fin, uint32_t flen, uint32_t *qout,
+                         uint32_t *fout, uint32_t thr_old, uint32_t thr_new, uint32_t round,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_il_far, dim3(wave_blocks(flen)), dim3(256), 0, st, a, fin, flen, qout,
+                       fout, thr_old, thr_new, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_il_count(const IlArgs &a, bool packed, bool in_arcs, uint32_t *qout,
+                           uint32_t round, hipStream_t st)
+{
+    const dim3 grid(wave_blocks((size_t)a.groups * (size_t)a.n)), block(256);
+    if (in_arcs) {
+        if (packed)
+            hipLaunchKernelGGL(k_il_count_in<true>, grid, block, 0, st, a, qout, round);
+        else
+            hipLaunchKernelGGL(k_il_count_in<false>, grid, block, 0, st, a, qout, round);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL(k_il_count_out<true>, grid, block, 0, st, a, qout, round);
+        else
+            hipLaunchKernelGGL(k_il_count_out<false>, grid, block, 0, st, a, qout, round);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_il_round(const IlArgs &a, bool packed, bool deps, const uint32_t *q,
+                           uint32_t qlen, uint32_t *qout, uint32_t round, hipStream_t st)
+{
+    const dim3 grid(wave_blocks(qlen)), block(256);
+    if (deps) {
+        if (packed)
+            hipLaunchKernelGGL(k_il_delta<true>, grid, block, 0, st, a, q, qlen, qout, round);
+        else
+            hipLaunchKernelGGL(k_il_delta<false>, grid, block, 0, st, a, q, qlen, qout, round);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL(k_il_sigma<true>, grid, block, 0, st, a, q, qlen, qout, round);
+        else
+            hipLaunchKernelGGL(k_il_sigma<false>, grid, block, 0, st, a, q, qlen, qout, round);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_il_bc(const IlArgs &a, double *bc, const int32_t *perm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_il_bc, dim3(wave_blocks((size_t)a.n)), dim3(256), 0, st, a, bc, perm);
+    return hipGetLastError();
+}
