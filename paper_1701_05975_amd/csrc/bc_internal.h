@@ -7,6 +7,7 @@
 
 #include "../../include/bc.h"
 #include "kernels.h"
+#include "interleaved.h"
 
 struct bc_error {
     bc_status status;

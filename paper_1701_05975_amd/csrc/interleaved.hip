@@ -28,7 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
-#include "kernels.h"
+#include "interleaved.h"
 
 namespace {
 

@@ -33,47 +33,6 @@ struct BatchArgs {
     unsigned long long *err;      // [0] error bits, [1] first overflowing source index
 };
 
-// Source-interleaved form: the state of `groups` groups of 64 sources; entry
-// e = group * n + vertex, and each state array holds one 64-lane row per entry
-// (lane b = the group's b-th source).
-struct IlCtl {
-    unsigned int qlen;     // entries appended to the output queue this launch
-    unsigned int flen;     // entries in the far list being built
-    unsigned int minkept;  // least distance kept in the far list by a far pass
-    unsigned int pad;
-    unsigned long long reached;
-};
-
-struct IlArgs {
-    DevGraph g;
-    int n, groups;
-    uint32_t *d;                // [entries][64] distances, BC_INF = unreached
-    unsigned long long *sigma;  // [entries][64] shortest-path counts
-    double *delta;              // [entries][64] dependencies
-    int32_t *cnt;               // [entries][64] pending DAG neighbours
-    unsigned long long *act;    // [entries] lanes to process when the entry is dequeued
-    unsigned long long *far;    // [entries] lanes with a distance beyond the band
-    uint32_t *stamp;            // [entries] last round that queued the entry
-    int32_t *lane_src;          // [groups * 64] internal source id, -1 = empty lane
-    IlCtl *ctl;
-    unsigned long long *err;    // [0] error bits, [1] first overflowing source-list index
-    long long src_base;         // source-list index of the sweep's first lane
-};
-
-hipError_t launch_il_init(const IlArgs &a, const int32_t *sources, long long k,
-                          const int32_t *iperm, uint32_t *qout, uint32_t round, hipStream_t st);
-hipError_t launch_il_relax(const IlArgs &a, bool packed, const uint32_t *q, uint32_t qlen,
-                           uint32_t *qout, uint32_t *fout, uint32_t thr, uint32_t round,
-                           hipStream_t st);
-hipError_t launch_il_far(const IlArgs &a, const uint32_t *fin, uint32_t flen, uint32_t *qout,
-                         uint32_t *fout, uint32_t thr_old, uint32_t thr_new, uint32_t round,
-                         hipStream_t st);
-hipError_t launch_il_count(const IlArgs &a, bool packed, bool in_arcs, uint32_t *qout,
-                           uint32_t round, hipStream_t st);
-hipError_t launch_il_round(const IlArgs &a, bool packed, bool deps, const uint32_t *q,
-                           uint32_t qlen, uint32_t *qout, uint32_t round, hipStream_t st);
-hipError_t launch_il_bc(const IlArgs &a, double *bc, const int32_t *perm, hipStream_t st);
-
 // Phase machine of the plain form (device memory, one per graph).
 struct PlainCtl {
     int phase;
