@@ -136,9 +136,9 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
               int64_t k);
 void reset_device_counters(bc_graph *g, hipStream_t st);
 void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);
-// Source-interleaved form: groups of 64 sources per sweep for n vertices, k
-// sources and the given free device bytes (0: not even one group fits).
-int interleaved_groups_per_sweep(int32_t n, int64_t k, size_t free_bytes);
+// Source-interleaved form: groups of 64 sources per sweep for n vertices, nnz
+// arcs, k sources and the given free device bytes (0: not even one fits).
+int interleaved_groups_per_sweep(int32_t n, int64_t nnz, int64_t k, size_t free_bytes);
 void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
                      double *bc_dev, DevCounters &cnt, float &ms);
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,

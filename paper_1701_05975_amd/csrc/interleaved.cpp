@@ -13,8 +13,12 @@ namespace {
 
 // Bytes per (group, vertex) entry: rows of distances (4), counts (8),
 // dependencies (8) and pending counts (4) for 64 lanes, the lane masks and
-// stamp, and the two queues and two far lists.
-constexpr size_t IL_ENTRY_BYTES = 64 * (4 + 8 + 8 + 4) + 8 + 8 + 4 + 4 * 4;
+// stamp, the two queues and two far lists, the taken mask and a work item.
+constexpr size_t IL_ENTRY_BYTES = 64 * (4 + 8 + 8 + 4) + 8 + 8 + 4 + 4 * 4 + 8 + 8;
+
+// Work items of one round beyond one per entry: a queue holds each entry at
+// most once, and a vertex of degree D gives ceil(D / IL_CHUNK) items.
+static size_t extra_items_per_group(int64_t nnz) { return (size_t)nnz / IL_CHUNK + 1; }
 constexpr size_t IL_BUDGET_CAP = 96ull << 30;
 
 template <class T> T *carve(char *&p, size_t count)
@@ -32,11 +36,12 @@ struct Staging {
 
 } // namespace
 
-int interleaved_groups_per_sweep(int32_t n, int64_t k, size_t free_bytes)
+int interleaved_groups_per_sweep(int32_t n, int64_t nnz, int64_t k, size_t free_bytes)
 {
     const int64_t total = (k + 63) / 64;
     const size_t budget = std::min(free_bytes / 10 * 6, IL_BUDGET_CAP);
-    int64_t gs = (int64_t)(budget / ((size_t)n * IL_ENTRY_BYTES));
+    const size_t per_group = (size_t)n * IL_ENTRY_BYTES + extra_items_per_group(nnz) * 8;
+    int64_t gs = (int64_t)(budget / per_group);
     gs = std::min<int64_t>(gs, total);
     gs = std::min<int64_t>(gs, (int64_t)(INT32_MAX / 2) / std::max<int32_t>(n, 1));
     return (int)std::max<int64_t>(gs, 0);
@@ -57,7 +62,7 @@ void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_d
     if (k > 0) {
         size_t free_b = 0, total_b = 0;
         hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-        int gs = interleaved_groups_per_sweep(n, k, free_b);
+        int gs = interleaved_groups_per_sweep(n, g->nnz, k, free_b);
         if (r.il_groups > 0 && gs > 0)
             gs = std::min(gs, r.il_groups);
         if (gs < 1)
@@ -65,8 +70,9 @@ void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_d
                            (size_t)n * IL_ENTRY_BYTES, free_b);
         const size_t entries = (size_t)gs * (size_t)n;
         const size_t cells = entries * 64;
-        const size_t need = cells * (4 + 8 + 8 + 4) + entries * (8 + 8 + 4 + 16) +
-                            (size_t)gs * 64 * 4 + 16 * 256 + sizeof(IlCtl);
+        const size_t items = entries + (size_t)gs * extra_items_per_group(g->nnz);
+        const size_t need = cells * (4 + 8 + 8 + 4) + entries * (8 + 8 + 4 + 16 + 8) +
+                            items * 8 + (size_t)gs * 64 * 4 + 20 * 256 + sizeof(IlCtl);
         DevBuf buf;
         buf.alloc(need);
         char *p = (char *)buf.p;
@@ -83,6 +89,8 @@ void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_d
         uint32_t *qa = carve<uint32_t>(p, entries), *qb = carve<uint32_t>(p, entries);
         uint32_t *fa = carve<uint32_t>(p, entries), *fb = carve<uint32_t>(p, entries);
         a.lane_src = carve<int32_t>(p, (size_t)gs * 64);
+        a.qm = carve<unsigned long long>(p, entries);
+        a.items = carve<unsigned long long>(p, items);
         a.ctl = carve<IlCtl>(p, 1);
         DevCounters *dc = (DevCounters *)g->ctl.p;
         a.err = dc->err;

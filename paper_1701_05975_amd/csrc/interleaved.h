@@ -10,11 +10,14 @@
 // Source-interleaved form: the state of `groups` groups of 64 sources; entry
 // e = group * n + vertex, and each state array holds one 64-lane row per entry
 // (lane b = the group's b-th source).
+// Arcs per work item of a round (a vertex with more arcs is split).
+#define IL_CHUNK 256u
+
 struct IlCtl {
     unsigned int qlen;     // entries appended to the output queue this launch
     unsigned int flen;     // entries in the far list being built
     unsigned int minkept;  // least distance kept in the far list by a far pass
-    unsigned int pad;
+    unsigned int ilen;     // work items of the current round
     unsigned long long reached;
 };
 
@@ -29,6 +32,8 @@ struct IlArgs {
     unsigned long long *far;    // [entries] lanes with a distance beyond the band
     uint32_t *stamp;            // [entries] last round that queued the entry
     int32_t *lane_src;          // [groups * 64] internal source id, -1 = empty lane
+    unsigned long long *qm;     // [entries] lane mask taken by each queue slot this round
+    unsigned long long *items;  // work items (queue slot << 32 | arc chunk) of the round
     IlCtl *ctl;
     unsigned long long *err;    // [0] error bits, [1] first overflowing source-list index
     long long src_base;         // source-list index of the sweep's first lane

@@ -27,6 +27,8 @@
 // reads the queue lengths between launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dev_common.h"
 #include "interleaved.h"
 
@@ -113,49 +115,119 @@ __global__ void k_il_seed(IlArgs a, const int32_t *sources, long long k, const i
     }
 }
 
-// One forward round: each queued vertex relaxes its out-arcs for the lanes in
-// its mask whose distance lies below the band threshold.
+// Start of a round: each queued entry takes its lane mask (later improvements
+// queue it again) and is split into work items of at most IL_CHUNK arcs, so
+// that the arcs of a high-degree vertex are walked by many waves at once.
+__global__ void k_il_take(IlArgs a, const uint32_t *q, uint32_t qlen, int in_arcs)
+{
+    const int lane = lane_id();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same iterations (wave-wide scan below)
+    const size_t span = ((size_t)qlen + stride - 1) / stride * stride;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += stride) {
+        uint32_t chunks = 0;
+        if (i < qlen) {
+            const uint32_t e = q[i];
+            const unsigned long long m = atomicExch(&a.act[e], 0ull);
+            a.qm[i] = m;
+            if (m) {
+                const uint32_t v = e % (uint32_t)a.n;
+                const uint32_t deg = in_arcs ? a.g.trow[v + 1] - a.g.trow[v]
+                                             : a.g.row[v + 1] - a.g.row[v];
+                chunks = (deg + IL_CHUNK - 1) / IL_CHUNK;
+            }
+        }
+        uint32_t incl = chunks;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o);
+            if (lane >= o)
+                incl += t;
+        }
+        const uint32_t total = __shfl(incl, WAVE - 1);
+        uint32_t base = 0;
+        if (lane == WAVE - 1 && total)
+            base = atomicAdd(&a.ctl->ilen, total);
+        base = __shfl(base, WAVE - 1);
+        const uint32_t first = base + incl - chunks;
+        for (uint32_t c = 0; c < chunks; ++c)
+            a.items[first + c] = (unsigned long long)i << 32 | c;
+    }
+}
+
+// A work item: queue slot i, arcs [c * IL_CHUNK, (c + 1) * IL_CHUNK) of the row.
+struct IlItem {
+    uint32_t e, grp, v, base, beg, end;
+    unsigned long long m;
+};
+
+__device__ __forceinline__ IlItem il_item(const IlArgs &a, const uint32_t *q,
+                                          const uint32_t *rows, uint32_t t)
+{
+    const unsigned long long it = a.items[t];
+    const uint32_t i = (uint32_t)(it >> 32), c = (uint32_t)it;
+    IlItem r;
+    r.e = q[i];
+    r.m = a.qm[i];
+    r.grp = r.e / (uint32_t)a.n;
+    r.v = r.e - r.grp * (uint32_t)a.n;
+    r.base = r.grp * (uint32_t)a.n;
+    const uint32_t b = rows[r.v], e = rows[r.v + 1];
+    r.beg = b + c * IL_CHUNK;
+    r.end = e - r.beg > IL_CHUNK ? r.beg + IL_CHUNK : e;
+    return r;
+}
+
+// Arcs handled together by a wave: their atomics are issued before any
+// result is used, so that their round trips overlap.
+#define IL_UNROLL 4
+
+// One forward round over the work items: the lanes of the item's mask whose
+// distance lies below the band threshold relax the item's arcs.
 template <bool PACKED>
-__global__ void k_il_relax(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
-                           uint32_t *fout, uint32_t thr, uint32_t round)
+__global__ void k_il_relax(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t *fout,
+                           uint32_t thr, uint32_t round)
 {
     const int lane = lane_id();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
-    for (uint32_t i = wid; i < qlen; i += nw) {
-        const uint32_t e = q[i];
-        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
-        unsigned long long m = 0;
-        if (lane == 0)
-            m = atomicExch(&a.act[e], 0ull);
-        m = first_lane_u64(m);
-        if (m == 0)
-            continue;
-        const bool on = (m >> lane) & 1ull;
-        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
+    const uint32_t ilen = a.ctl->ilen;
+    for (uint32_t t = wid; t < ilen; t += nw) {
+        const IlItem it = il_item(a, q, g.row, t);
+        const bool on = (it.m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
         const bool live = on && dv < thr;
-        const uint32_t base = grp * (uint32_t)a.n;
-        const uint32_t beg = g.row[v], end = g.row[v + 1];
-        for (uint32_t j = beg; j < end; ++j) {
-            uint32_t u, w;
-            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
-            const uint32_t eu = base + u;
-            bool imp = false;
-            uint32_t nd = 0;
-            if (live) {
-                nd = dv + w;
-                imp = nd < atomicMin(&a.d[cell(eu, lane)], nd);
+        for (uint32_t j = it.beg; j < it.end; j += IL_UNROLL) {
+            uint32_t u[IL_UNROLL], nd[IL_UNROLL], old[IL_UNROLL];
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                uint32_t w = 0;
+                u[k] = 0;
+                if (j + k < it.end)
+                    arc_at<PACKED>(g.arc, g.wt, j + k, g.wshift, g.wmask, u[k], w);
+                nd[k] = dv + w;
+                old[k] = 0;
             }
-            const unsigned long long bn = __ballot(imp && nd < thr);
-            const unsigned long long bf = __ballot(imp && nd >= thr);
-            if (lane == 0) {
-                if (bn) {
-                    atomicOr(&a.act[eu], bn);
-                    queue_once(a, eu, round, qout, &a.ctl->qlen);
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                if (live && j + k < it.end)
+                    old[k] = atomicMin(&a.d[cell(it.base + u[k], lane)], nd[k]);
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                if (j + k >= it.end)
+                    break;
+                const bool imp = live && nd[k] < old[k];
+                const unsigned long long bn = __ballot(imp && nd[k] < thr);
+                const unsigned long long bf = __ballot(imp && nd[k] >= thr);
+                const uint32_t eu = it.base + u[k];
+                if (lane == 0) {
+                    if (bn) {
+                        atomicOr(&a.act[eu], bn);
+                        queue_once(a, eu, round, qout, &a.ctl->qlen);
+                    }
+                    if (bf && atomicOr(&a.far[eu], bf) == 0ull)
+                        fout[atomicAdd(&a.ctl->flen, 1u)] = eu;
                 }
-                if (bf && atomicOr(&a.far[eu], bf) == 0ull)
-                    fout[atomicAdd(&a.ctl->flen, 1u)] = eu;
             }
         }
     }
@@ -234,35 +306,28 @@ __global__ void k_il_count_in(IlArgs a, uint32_t *qout, uint32_t round)
     }
 }
 
-// One count round: vertices whose count is final for the lanes in their mask
-// add it into their tight out-neighbours; a neighbour whose last pending
-// predecessor this was becomes final for that lane and is queued.
+// One count round over the work items: vertices whose count is final for the
+// lanes in their mask add it into their tight out-neighbours; a neighbour
+// whose last pending predecessor this was becomes final for that lane and is
+// queued.
 template <bool PACKED>
-__global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
-                           uint32_t round)
+__global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t round)
 {
     const int lane = lane_id();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
-    for (uint32_t i = wid; i < qlen; i += nw) {
-        const uint32_t e = q[i];
-        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
-        unsigned long long m = 0;
-        if (lane == 0)
-            m = atomicExch(&a.act[e], 0ull);
-        m = first_lane_u64(m);
-        if (m == 0)
-            continue;
-        const bool on = (m >> lane) & 1ull;
-        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
-        const unsigned long long sv = on ? a.sigma[cell(e, lane)] : 0ull;
-        const uint32_t base = grp * (uint32_t)a.n;
+    const uint32_t ilen = a.ctl->ilen;
+    for (uint32_t t = wid; t < ilen; t += nw) {
+        const IlItem it = il_item(a, q, g.row, t);
+        const bool on = (it.m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
+        const unsigned long long sv = on ? a.sigma[cell(it.e, lane)] : 0ull;
         bool ovf = false;
-        for (uint32_t j = g.row[v]; j < g.row[v + 1]; ++j) {
+        for (uint32_t j = it.beg; j < it.end; ++j) {
             uint32_t u, w;
             arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
-            const uint32_t eu = base + u;
+            const uint32_t eu = it.base + u;
             bool ready = false;
             const uint32_t du = on ? a.d[cell(eu, lane)] : BC_INF;
             if (du != BC_INF && du == (uint64_t)dv + w) {
@@ -278,7 +343,8 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t 
         }
         if (ovf) {
             atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_SIGMA);
-            atomicMin(&a.err[1], (unsigned long long)(a.src_base + (long long)grp * WAVE + lane));
+            atomicMin(&a.err[1],
+                      (unsigned long long)(a.src_base + (long long)it.grp * WAVE + lane));
         }
     }
 }
@@ -319,35 +385,28 @@ __global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
     }
 }
 
-// One dependency round: vertices whose dependency is final for the lanes in
-// their mask push sigma_p / sigma_v (1 + delta_v) into each tight predecessor
-// p; a predecessor whose last pending successor this was is queued.
+// One dependency round over the work items (in-arcs): vertices whose
+// dependency is final for the lanes in their mask push sigma_p / sigma_v
+// (1 + delta_v) into each tight predecessor p; a predecessor whose last
+// pending successor this was is queued.
 template <bool PACKED>
-__global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t qlen, uint32_t *qout,
-                           uint32_t round)
+__global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t round)
 {
     const int lane = lane_id();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
-    for (uint32_t i = wid; i < qlen; i += nw) {
-        const uint32_t e = q[i];
-        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
-        unsigned long long m = 0;
-        if (lane == 0)
-            m = atomicExch(&a.act[e], 0ull);
-        m = first_lane_u64(m);
-        if (m == 0)
-            continue;
-        const bool on = (m >> lane) & 1ull;
-        const uint32_t dv = on ? a.d[cell(e, lane)] : BC_INF;
-        const double sv = on ? (double)a.sigma[cell(e, lane)] : 1.0;
-        const double f = on ? 1.0 + a.delta[cell(e, lane)] : 0.0;
-        const uint32_t base = grp * (uint32_t)a.n;
-        for (uint32_t j = g.trow[v]; j < g.trow[v + 1]; ++j) {
+    const uint32_t ilen = a.ctl->ilen;
+    for (uint32_t t = wid; t < ilen; t += nw) {
+        const IlItem it = il_item(a, q, g.trow, t);
+        const bool on = (it.m >> lane) & 1ull;
+        const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
+        const double sv = on ? (double)a.sigma[cell(it.e, lane)] : 1.0;
+        const double f = on ? 1.0 + a.delta[cell(it.e, lane)] : 0.0;
+        for (uint32_t j = it.beg; j < it.end; ++j) {
             uint32_t p, w;
             arc_at<PACKED>(g.tarc, g.twt, j, g.wshift, g.wmask, p, w);
-            const uint32_t ep = base + p;
+            const uint32_t ep = it.base + p;
             bool ready = false;
             if (on) {
                 const uint32_t dp = a.d[cell(ep, lane)];
@@ -409,17 +468,22 @@ hipError_t launch_il_init(const IlArgs &a, const int32_t *sources, long long k,
     return hipGetLastError();
 }
 
+static int item_blocks(uint32_t qlen)
+{
+    // at least 2048 blocks, so that the chunks of high-degree vertices spread
+    return std::max(wave_blocks(qlen), 2048);
+}
+
 hipError_t launch_il_relax(const IlArgs &a, bool packed, const uint32_t *q, uint32_t qlen,
                            uint32_t *qout, uint32_t *fout, uint32_t thr, uint32_t round,
                            hipStream_t st)
 {
-    const dim3 grid(wave_blocks(qlen)), block(256);
+    hipLaunchKernelGGL(k_il_take, dim3((qlen + 255) / 256), dim3(256), 0, st, a, q, qlen, 0);
+    const dim3 grid(item_blocks(qlen)), block(256);
     if (packed)
-        hipLaunchKernelGGL(k_il_relax<true>, grid, block, 0, st, a, q, qlen, qout, fout, thr,
-                           round);
+        hipLaunchKernelGGL(k_il_relax<true>, grid, block, 0, st, a, q, qout, fout, thr, round);
     else
-        hipLaunchKernelGGL(k_il_relax<false>, grid, block, 0, st, a, q, qlen, qout, fout, thr,
-                           round);
+        hipLaunchKernelGGL(k_il_relax<false>, grid, block, 0, st, a, q, qout, fout, thr, round);
     return hipGetLastError();
 }
 
@@ -453,17 +517,19 @@ hipError_t launch_il_count(const IlArgs &a, bool packed, bool in_arcs, uint32_t 
 hipError_t launch_il_round(const IlArgs &a, bool packed, bool deps, const uint32_t *q,
                            uint32_t qlen, uint32_t *qout, uint32_t round, hipStream_t st)
 {
-    const dim3 grid(wave_blocks(qlen)), block(256);
+    hipLaunchKernelGGL(k_il_take, dim3((qlen + 255) / 256), dim3(256), 0, st, a, q, qlen,
+                       deps ? 1 : 0);
+    const dim3 grid(item_blocks(qlen)), block(256);
     if (deps) {
         if (packed)
-            hipLaunchKernelGGL(k_il_delta<true>, grid, block, 0, st, a, q, qlen, qout, round);
+            hipLaunchKernelGGL(k_il_delta<true>, grid, block, 0, st, a, q, qout, round);
         else
-            hipLaunchKernelGGL(k_il_delta<false>, grid, block, 0, st, a, q, qlen, qout, round);
+            hipLaunchKernelGGL(k_il_delta<false>, grid, block, 0, st, a, q, qout, round);
     } else {
         if (packed)
-            hipLaunchKernelGGL(k_il_sigma<true>, grid, block, 0, st, a, q, qlen, qout, round);
+            hipLaunchKernelGGL(k_il_sigma<true>, grid, block, 0, st, a, q, qout, round);
         else
-            hipLaunchKernelGGL(k_il_sigma<false>, grid, block, 0, st, a, q, qlen, qout, round);
+            hipLaunchKernelGGL(k_il_sigma<false>, grid, block, 0, st, a, q, qout, round);
     }
     return hipGetLastError();
 }
