@@ -54,6 +54,49 @@ __device__ __forceinline__ void queue_once(const IlArgs &a, uint32_t e, uint32_t
         qout[atomicAdd(qlen, 1u)] = e;
 }
 
+// Appends of one wave to a queue, staged in registers (lane k holds slot k):
+// one atomic on the queue's length per 64 entries instead of one per entry,
+// as every wave of the grid appends to the same queue.  Every lane of the
+// wave calls push and flush with the same arguments.
+struct WaveQueue {
+    uint32_t *out;
+    unsigned int *len;
+    uint32_t slot;
+    int n;
+    __device__ __forceinline__ WaveQueue(uint32_t *o, unsigned int *l) : out(o), len(l), slot(0), n(0) {}
+    __device__ __forceinline__ void flush(int lane)
+    {
+        if (n == 0)
+            return;
+        uint32_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(len, (unsigned int)n);
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (lane < n)
+            out[base + lane] = slot;
+        n = 0;
+    }
+    __device__ __forceinline__ void push(uint32_t e, int lane)
+    {
+        if (lane == n)
+            slot = e;
+        if (++n == WAVE)
+            flush(lane);
+    }
+};
+
+// Queues entry e (through the wave's stager) unless this round already
+// queued it; lane 0 takes the stamp.
+__device__ __forceinline__ void queue_once_w(const IlArgs &a, uint32_t e, uint32_t round,
+                                             WaveQueue &wq, int lane)
+{
+    uint32_t fresh = 0;
+    if (lane == 0)
+        fresh = atomicExch(&a.stamp[e], round) != round ? 1u : 0u;
+    if (__builtin_amdgcn_readfirstlane(fresh))
+        wq.push(e, lane);
+}
+
 __device__ __forceinline__ double wave_sum_f64(double x)
 {
     for (int o = 32; o > 0; o >>= 1)
@@ -192,6 +235,7 @@ __global__ void k_il_relax(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
     const uint32_t ilen = a.ctl->ilen;
+    WaveQueue qq(qout, &a.ctl->qlen), fq(fout, &a.ctl->flen);
     for (uint32_t t = wid; t < ilen; t += nw) {
         const IlItem it = il_item(a, q, g.row, t);
         const bool on = (it.m >> lane) & 1ull;
@@ -220,17 +264,23 @@ __global__ void k_il_relax(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
                 const unsigned long long bn = __ballot(imp && nd[k] < thr);
                 const unsigned long long bf = __ballot(imp && nd[k] >= thr);
                 const uint32_t eu = it.base + u[k];
-                if (lane == 0) {
-                    if (bn) {
+                if (bn) {
+                    if (lane == 0)
                         atomicOr(&a.act[eu], bn);
-                        queue_once(a, eu, round, qout, &a.ctl->qlen);
-                    }
-                    if (bf && atomicOr(&a.far[eu], bf) == 0ull)
-                        fout[atomicAdd(&a.ctl->flen, 1u)] = eu;
+                    queue_once_w(a, eu, round, qq, lane);
+                }
+                if (bf) {
+                    uint32_t first = 0;
+                    if (lane == 0)
+                        first = atomicOr(&a.far[eu], bf) == 0ull ? 1u : 0u;
+                    if (__builtin_amdgcn_readfirstlane(first))
+                        fq.push(eu, lane);
                 }
             }
         }
     }
+    qq.flush(lane);
+    fq.flush(lane);
 }
 
 // Far-list pass when the band threshold moves from thr_old to thr_new: lanes
@@ -242,6 +292,8 @@ __global__ void k_il_far(IlArgs a, const uint32_t *fin, uint32_t flen, uint32_t 
     const int lane = lane_id();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    WaveQueue qq(qout, &a.ctl->qlen), fq(fout, &a.ctl->flen);
+    uint32_t wmin = BC_INF;
     for (uint32_t i = wid; i < flen; i += nw) {
         const uint32_t e = fin[i];
         const unsigned long long fm = first_lane_u64(lane == 0 ? a.far[e] : 0ull);
@@ -252,18 +304,21 @@ __global__ void k_il_far(IlArgs a, const uint32_t *fin, uint32_t flen, uint32_t 
         const bool keep = on && !drop && !move;
         const unsigned long long km = __ballot(keep), mv = __ballot(move);
         const uint32_t kmin = wave_min_u32_il(keep ? dv : BC_INF);
-        if (lane == 0) {
+        wmin = kmin < wmin ? kmin : wmin;
+        if (lane == 0)
             a.far[e] = km;
-            if (mv) {
+        if (mv) {
+            if (lane == 0)
                 atomicOr(&a.act[e], mv);
-                queue_once(a, e, round, qout, &a.ctl->qlen);
-            }
-            if (km) {
-                fout[atomicAdd(&a.ctl->flen, 1u)] = e;
-                atomicMin(&a.ctl->minkept, kmin);
-            }
+            queue_once_w(a, e, round, qq, lane);
         }
+        if (km)
+            fq.push(e, lane);
     }
+    qq.flush(lane);
+    fq.flush(lane);
+    if (lane == 0 && wmin != BC_INF)
+        atomicMin(&a.ctl->minkept, wmin);
 }
 
 // Tight in-arcs per (vertex, source): the number of DAG predecessors whose
@@ -277,6 +332,8 @@ __global__ void k_il_count_in(IlArgs a, uint32_t *qout, uint32_t round)
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
+    WaveQueue qq(qout, &a.ctl->qlen);
+    unsigned long long nreached = 0;
     for (uint32_t e = wid; e < entries; e += nw) {
         const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
         const uint32_t dv = a.d[cell(e, lane)];
@@ -295,15 +352,16 @@ __global__ void k_il_count_in(IlArgs a, uint32_t *qout, uint32_t round)
         }
         a.cnt[cell(e, lane)] = c;
         const unsigned long long ready = __ballot(reached && c == 0);
-        const unsigned long long nr = __ballot(reached);
-        if (lane == 0) {
-            atomicAdd(&a.ctl->reached, (unsigned long long)__popcll(nr));
-            if (ready) {
+        nreached += (unsigned long long)__popcll(__ballot(reached));
+        if (ready) {
+            if (lane == 0)
                 a.act[e] = ready;
-                queue_once(a, e, round, qout, &a.ctl->qlen);
-            }
+            queue_once_w(a, e, round, qq, lane);
         }
     }
+    qq.flush(lane);
+    if (lane == 0 && nreached)
+        atomicAdd(&a.ctl->reached, nreached);
 }
 
 // One count round over the work items: vertices whose count is final for the
@@ -318,6 +376,7 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
     const uint32_t ilen = a.ctl->ilen;
+    WaveQueue qq(qout, &a.ctl->qlen);
     for (uint32_t t = wid; t < ilen; t += nw) {
         const IlItem it = il_item(a, q, g.row, t);
         const bool on = (it.m >> lane) & 1ull;
@@ -336,9 +395,10 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
                 ready = atomicSub(&a.cnt[cell(eu, lane)], 1) == 1;
             }
             const unsigned long long br = __ballot(ready);
-            if (lane == 0 && br) {
-                atomicOr(&a.act[eu], br);
-                queue_once(a, eu, round, qout, &a.ctl->qlen);
+            if (br) {
+                if (lane == 0)
+                    atomicOr(&a.act[eu], br);
+                queue_once_w(a, eu, round, qq, lane);
             }
         }
         if (ovf) {
@@ -347,6 +407,7 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
                       (unsigned long long)(a.src_base + (long long)it.grp * WAVE + lane));
         }
     }
+    qq.flush(lane);
 }
 
 // Tight out-arcs per (vertex, source): the DAG successors whose dependencies
@@ -360,6 +421,7 @@ __global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
+    WaveQueue qq(qout, &a.ctl->qlen);
     for (uint32_t e = wid; e < entries; e += nw) {
         const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
         const uint32_t dv = a.d[cell(e, lane)];
@@ -378,11 +440,13 @@ __global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
         }
         a.cnt[cell(e, lane)] = c;
         const unsigned long long leaves = __ballot(reached && c == 0);
-        if (lane == 0 && leaves) {
-            a.act[e] = leaves;
-            queue_once(a, e, round, qout, &a.ctl->qlen);
+        if (leaves) {
+            if (lane == 0)
+                a.act[e] = leaves;
+            queue_once_w(a, e, round, qq, lane);
         }
     }
+    qq.flush(lane);
 }
 
 // One dependency round over the work items (in-arcs): vertices whose
@@ -397,6 +461,7 @@ __global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
     const DevGraph &g = a.g;
     const uint32_t ilen = a.ctl->ilen;
+    WaveQueue qq(qout, &a.ctl->qlen);
     for (uint32_t t = wid; t < ilen; t += nw) {
         const IlItem it = il_item(a, q, g.trow, t);
         const bool on = (it.m >> lane) & 1ull;
@@ -417,12 +482,14 @@ __global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
                 }
             }
             const unsigned long long br = __ballot(ready);
-            if (lane == 0 && br) {
-                atomicOr(&a.act[ep], br);
-                queue_once(a, ep, round, qout, &a.ctl->qlen);
+            if (br) {
+                if (lane == 0)
+                    atomicOr(&a.act[ep], br);
+                queue_once_w(a, ep, round, qq, lane);
             }
         }
     }
+    qq.flush(lane);
 }
 
 // bc[v] += the dependencies of v over every lane of every group whose source
