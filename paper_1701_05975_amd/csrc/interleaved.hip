@@ -342,13 +342,22 @@ __global__ void k_il_count_in(IlArgs a, uint32_t *qout, uint32_t round)
             continue;
         const uint32_t base = grp * (uint32_t)a.n;
         int32_t c = 0;
-        for (uint32_t j = g.trow[v]; j < g.trow[v + 1]; ++j) {
-            uint32_t p, w;
-            arc_at<PACKED>(g.tarc, g.twt, j, g.wshift, g.wmask, p, w);
-            if (reached) {
-                const uint32_t dp = a.d[cell(base + p, lane)];
-                c += (dp != BC_INF && (uint64_t)dp + w == dv) ? 1 : 0;
+        const uint32_t tb = g.trow[v], te = g.trow[v + 1];
+        for (uint32_t j = tb; j < te; j += IL_UNROLL) {
+            uint32_t p[IL_UNROLL], w[IL_UNROLL], dp[IL_UNROLL];
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                p[k] = 0;
+                w[k] = 0;
+                if (j + k < te)
+                    arc_at<PACKED>(g.tarc, g.twt, j + k, g.wshift, g.wmask, p[k], w[k]);
             }
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                dp[k] = reached && j + k < te ? a.d[cell(base + p[k], lane)] : BC_INF;
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                c += (dp[k] != BC_INF && (uint64_t)dp[k] + w[k] == dv) ? 1 : 0;
         }
         a.cnt[cell(e, lane)] = c;
         const unsigned long long ready = __ballot(reached && c == 0);
@@ -383,22 +392,43 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
         const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
         const unsigned long long sv = on ? a.sigma[cell(it.e, lane)] : 0ull;
         bool ovf = false;
-        for (uint32_t j = it.beg; j < it.end; ++j) {
-            uint32_t u, w;
-            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
-            const uint32_t eu = it.base + u;
-            bool ready = false;
-            const uint32_t du = on ? a.d[cell(eu, lane)] : BC_INF;
-            if (du != BC_INF && du == (uint64_t)dv + w) {
-                const unsigned long long old = atomicAdd(&a.sigma[cell(eu, lane)], sv);
-                ovf |= old + sv < old;
-                ready = atomicSub(&a.cnt[cell(eu, lane)], 1) == 1;
+        for (uint32_t j = it.beg; j < it.end; j += IL_UNROLL) {
+            uint32_t u[IL_UNROLL], du[IL_UNROLL], w[IL_UNROLL];
+            unsigned long long old[IL_UNROLL];
+            int32_t left[IL_UNROLL];
+            bool tight[IL_UNROLL];
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                u[k] = 0;
+                w[k] = 0;
+                if (j + k < it.end)
+                    arc_at<PACKED>(g.arc, g.wt, j + k, g.wshift, g.wmask, u[k], w[k]);
             }
-            const unsigned long long br = __ballot(ready);
-            if (br) {
-                if (lane == 0)
-                    atomicOr(&a.act[eu], br);
-                queue_once_w(a, eu, round, qq, lane);
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                du[k] = on && j + k < it.end ? a.d[cell(it.base + u[k], lane)] : BC_INF;
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                tight[k] = du[k] != BC_INF && du[k] == (uint64_t)dv + w[k];
+                old[k] = 0;
+                left[k] = 0;
+                if (tight[k]) {
+                    old[k] = atomicAdd(&a.sigma[cell(it.base + u[k], lane)], sv);
+                    left[k] = atomicSub(&a.cnt[cell(it.base + u[k], lane)], 1);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                if (j + k >= it.end)
+                    break;
+                ovf |= tight[k] && old[k] + sv < old[k];
+                const unsigned long long br = __ballot(tight[k] && left[k] == 1);
+                if (br) {
+                    const uint32_t eu = it.base + u[k];
+                    if (lane == 0)
+                        atomicOr(&a.act[eu], br);
+                    queue_once_w(a, eu, round, qq, lane);
+                }
             }
         }
         if (ovf) {
@@ -430,13 +460,22 @@ __global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
             continue;
         const uint32_t base = grp * (uint32_t)a.n;
         int32_t c = 0;
-        for (uint32_t j = g.row[v]; j < g.row[v + 1]; ++j) {
-            uint32_t u, w;
-            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
-            if (reached) {
-                const uint32_t du = a.d[cell(base + u, lane)];
-                c += (du != BC_INF && du == (uint64_t)dv + w) ? 1 : 0;
+        const uint32_t rb = g.row[v], re = g.row[v + 1];
+        for (uint32_t j = rb; j < re; j += IL_UNROLL) {
+            uint32_t u[IL_UNROLL], w[IL_UNROLL], du[IL_UNROLL];
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                u[k] = 0;
+                w[k] = 0;
+                if (j + k < re)
+                    arc_at<PACKED>(g.arc, g.wt, j + k, g.wshift, g.wmask, u[k], w[k]);
             }
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                du[k] = reached && j + k < re ? a.d[cell(base + u[k], lane)] : BC_INF;
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                c += (du[k] != BC_INF && du[k] == (uint64_t)dv + w[k]) ? 1 : 0;
         }
         a.cnt[cell(e, lane)] = c;
         const unsigned long long leaves = __ballot(reached && c == 0);
@@ -468,24 +507,42 @@ __global__ void k_il_delta(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
         const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
         const double sv = on ? (double)a.sigma[cell(it.e, lane)] : 1.0;
         const double f = on ? 1.0 + a.delta[cell(it.e, lane)] : 0.0;
-        for (uint32_t j = it.beg; j < it.end; ++j) {
-            uint32_t p, w;
-            arc_at<PACKED>(g.tarc, g.twt, j, g.wshift, g.wmask, p, w);
-            const uint32_t ep = it.base + p;
-            bool ready = false;
-            if (on) {
-                const uint32_t dp = a.d[cell(ep, lane)];
-                if (dp != BC_INF && (uint64_t)dp + w == dv) {
-                    const double sp = (double)a.sigma[cell(ep, lane)];
-                    atomicAdd(&a.delta[cell(ep, lane)], sp / sv * f);
-                    ready = atomicSub(&a.cnt[cell(ep, lane)], 1) == 1;
+        for (uint32_t j = it.beg; j < it.end; j += IL_UNROLL) {
+            uint32_t p[IL_UNROLL], dp[IL_UNROLL], w[IL_UNROLL];
+            int32_t left[IL_UNROLL];
+            bool tight[IL_UNROLL];
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                p[k] = 0;
+                w[k] = 0;
+                if (j + k < it.end)
+                    arc_at<PACKED>(g.tarc, g.twt, j + k, g.wshift, g.wmask, p[k], w[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k)
+                dp[k] = on && j + k < it.end ? a.d[cell(it.base + p[k], lane)] : BC_INF;
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                tight[k] = dp[k] != BC_INF && (uint64_t)dp[k] + w[k] == dv;
+                left[k] = 0;
+                if (tight[k]) {
+                    const size_t c = cell(it.base + p[k], lane);
+                    const double sp = (double)a.sigma[c];
+                    atomicAdd(&a.delta[c], sp / sv * f);
+                    left[k] = atomicSub(&a.cnt[c], 1);
                 }
             }
-            const unsigned long long br = __ballot(ready);
-            if (br) {
-                if (lane == 0)
-                    atomicOr(&a.act[ep], br);
-                queue_once_w(a, ep, round, qq, lane);
+#pragma unroll
+            for (int k = 0; k < IL_UNROLL; ++k) {
+                if (j + k >= it.end)
+                    break;
+                const unsigned long long br = __ballot(tight[k] && left[k] == 1);
+                if (br) {
+                    const uint32_t ep = it.base + p[k];
+                    if (lane == 0)
+                        atomicOr(&a.act[ep], br);
+                    queue_once_w(a, ep, round, qq, lane);
+                }
             }
         }
     }
