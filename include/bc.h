@@ -125,7 +125,8 @@ typedef struct {
     int32_t mode;         /* bc_mode */
     int32_t batch;        /* batched: sources in flight (state slabs); 0 = fill the GPU;
                              interleaved: at most this many sources per sweep */
-    int32_t delta;        /* near-far band width in weight units (>= 1); 0 = heuristic */
+    int32_t delta;        /* near-far band width in weight units (>= 1); 0 = heuristic (the
+                             interleaved form: at least 4 times the maximum weight) */
     int32_t lane_max_deg; /* count and dependency passes: vertices with at most this many
                              in-arcs (recorded predecessors) are handled by one lane, larger
                              ones by a whole 64-lane wave */

@@ -585,6 +585,11 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     if (r.wg_threads != 256 && r.wg_threads != 512 && r.wg_threads != 1024)
         throw bc_error(BC_E_INVAL, "wg_threads must be 256, 512 or 1024");
     r.delta = o.delta ? o.delta : default_delta(g);
+    if (r.mode == BC_MODE_INTERLEAVED && !o.delta) {
+        // every band of the interleaved form costs a far-list pass and its rounds
+        // a read-back each: wide bands (a few maximum weights) pay off there
+        r.delta = (int)std::max<int64_t>(r.delta, std::min<int64_t>(4ll * g->wmax, INT32_MAX / 2));
+    }
     r.lane_max = o.lane_max_deg ? o.lane_max_deg : 32;
     r.accumulate = o.accumulate ? o.accumulate : 1;
     r.dep_mode = o.dep_mode ? o.dep_mode : 1;
