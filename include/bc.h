@@ -111,9 +111,11 @@ typedef enum {
                                source, the state of a group laid out [vertex][source] so that
                                an arc read serves all 64 sources; rounds over queues of
                                (group, vertex) entries, as many groups per sweep as 60% of the
-                               free device memory (at most 96 GiB) holds, or batch
+                               free device memory (at most 160 GiB) holds, or batch
                                sources (rounded up to a multiple of 64) when batch > 0;
-                               lane and workgroup options do not apply */
+                               lane and workgroup options do not apply; edge
+                               betweenness and bc_source_state need the other forms
+                               (BC_E_INVAL) */
 } bc_mode;
 
 /*

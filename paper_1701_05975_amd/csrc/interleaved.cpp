@@ -19,7 +19,7 @@ constexpr size_t IL_ENTRY_BYTES = 64 * (4 + 8 + 8 + 4) + 8 + 8 + 4 + 4 * 4 + 8 +
 // Work items of one round beyond one per entry: a queue holds each entry at
 // most once, and a vertex of degree D gives ceil(D / IL_CHUNK) items.
 static size_t extra_items_per_group(int64_t nnz) { return (size_t)nnz / IL_CHUNK + 1; }
-constexpr size_t IL_BUDGET_CAP = 96ull << 30;
+constexpr size_t IL_BUDGET_CAP = 160ull << 30;
 
 template <class T> T *carve(char *&p, size_t count)
 {

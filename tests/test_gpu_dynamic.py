@@ -70,8 +70,9 @@ def test_update_matches_oracle(g, kind, seed):
 
 
 @pytest.mark.parametrize("opts", [dict(keep_order=True), dict(mode=bc.BC_MODE_PLAIN),
-                                  dict(accumulate=2, wg_threads=256, batch=7)],
-                         ids=["keep_order", "plain", "atomic"])
+                                  dict(accumulate=2, wg_threads=256, batch=7),
+                                  dict(mode=bc.BC_MODE_INTERLEAVED)],
+                         ids=["keep_order", "plain", "atomic", "interleaved"])
 def test_update_options(opts):
     opts = dict(opts)
     keep = opts.pop("keep_order", False)
