@@ -18,9 +18,10 @@
 //               sources start, and a vertex whose count reaches zero for a
 //               source has its final sigma and pushes it along its tight
 //               out-arcs (Alg. 2's counting rule, in Kahn's order);
-//   deps     -- the same in reverse: tight out-arcs counted, the DAG's leaves
-//               start, and a final vertex pushes sigma_u/sigma_w (1 + delta_w)
-//               into its tight predecessors (Alg. 3);
+//   deps     -- the same in reverse: the count pass leaves each vertex's number
+//               of tight out-arcs, the DAG's leaves start, and a final vertex
+//               pushes sigma_u/sigma_w (1 + delta_w) into its tight
+//               predecessors (Alg. 3);
 //   BC       -- each vertex adds its dependencies over the lanes whose source
 //               is another vertex (Alg. 3), in a fixed order.
 // Every round is one launch over a queue of (group, vertex) entries; the host
@@ -392,6 +393,7 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
         const uint32_t dv = on ? a.d[cell(it.e, lane)] : BC_INF;
         const unsigned long long sv = on ? a.sigma[cell(it.e, lane)] : 0ull;
         bool ovf = false;
+        int32_t ntight = 0;
         for (uint32_t j = it.beg; j < it.end; j += IL_UNROLL) {
             uint32_t u[IL_UNROLL], du[IL_UNROLL], w[IL_UNROLL];
             unsigned long long old[IL_UNROLL];
@@ -410,6 +412,7 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
 #pragma unroll
             for (int k = 0; k < IL_UNROLL; ++k) {
                 tight[k] = du[k] != BC_INF && du[k] == (uint64_t)dv + w[k];
+                ntight += tight[k] ? 1 : 0;
                 old[k] = 0;
                 left[k] = 0;
                 if (tight[k]) {
@@ -431,6 +434,10 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
                 }
             }
         }
+        // the vertex's pending count is zero now (its count is final): it
+        // becomes the number of its DAG successors, for the dependency pass
+        if (ntight)
+            atomicAdd(&a.cnt[cell(it.e, lane)], ntight);
         if (ovf) {
             atomicOr(&a.err[0], (unsigned long long)BC_ERRBIT_SIGMA);
             atomicMin(&a.err[1],
@@ -440,45 +447,19 @@ __global__ void k_il_sigma(IlArgs a, const uint32_t *q, uint32_t *qout, uint32_t
     qq.flush(lane);
 }
 
-// Tight out-arcs per (vertex, source): the DAG successors whose dependencies
-// must arrive first.  The reached vertices without one (the DAG's leaves) are
-// queued.
-template <bool PACKED>
-__global__ void k_il_count_out(IlArgs a, uint32_t *qout, uint32_t round)
+// Start of the dependency pass: the count pass left, per reached (vertex,
+// source), the number of its DAG successors; the reached ones without any
+// (the DAG's leaves) are queued.
+__global__ void k_il_leaves(IlArgs a, uint32_t *qout, uint32_t round)
 {
     const int lane = lane_id();
     const uint32_t entries = (uint32_t)a.groups * (uint32_t)a.n;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
-    const DevGraph &g = a.g;
     WaveQueue qq(qout, &a.ctl->qlen);
     for (uint32_t e = wid; e < entries; e += nw) {
-        const uint32_t grp = e / (uint32_t)a.n, v = e - grp * (uint32_t)a.n;
-        const uint32_t dv = a.d[cell(e, lane)];
-        const bool reached = dv != BC_INF;
-        if (__ballot(reached) == 0ull)
-            continue;
-        const uint32_t base = grp * (uint32_t)a.n;
-        int32_t c = 0;
-        const uint32_t rb = g.row[v], re = g.row[v + 1];
-        for (uint32_t j = rb; j < re; j += IL_UNROLL) {
-            uint32_t u[IL_UNROLL], w[IL_UNROLL], du[IL_UNROLL];
-#pragma unroll
-            for (int k = 0; k < IL_UNROLL; ++k) {
-                u[k] = 0;
-                w[k] = 0;
-                if (j + k < re)
-                    arc_at<PACKED>(g.arc, g.wt, j + k, g.wshift, g.wmask, u[k], w[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < IL_UNROLL; ++k)
-                du[k] = reached && j + k < re ? a.d[cell(base + u[k], lane)] : BC_INF;
-#pragma unroll
-            for (int k = 0; k < IL_UNROLL; ++k)
-                c += (du[k] != BC_INF && du[k] == (uint64_t)dv + w[k]) ? 1 : 0;
-        }
-        a.cnt[cell(e, lane)] = c;
-        const unsigned long long leaves = __ballot(reached && c == 0);
+        const bool reached = a.d[cell(e, lane)] != BC_INF;
+        const unsigned long long leaves = __ballot(reached && a.cnt[cell(e, lane)] == 0);
         if (leaves) {
             if (lane == 0)
                 a.act[e] = leaves;
@@ -630,10 +611,7 @@ hipError_t launch_il_count(const IlArgs &a, bool packed, bool in_arcs, uint32_t 
         else
             hipLaunchKernelGGL(k_il_count_in<false>, grid, block, 0, st, a, qout, round);
     } else {
-        if (packed)
-            hipLaunchKernelGGL(k_il_count_out<true>, grid, block, 0, st, a, qout, round);
-        else
-            hipLaunchKernelGGL(k_il_count_out<false>, grid, block, 0, st, a, qout, round);
+        hipLaunchKernelGGL(k_il_leaves, grid, block, 0, st, a, qout, round);
     }
     return hipGetLastError();
 }
