@@ -44,6 +44,9 @@ int interleaved_groups_per_sweep(int32_t n, int64_t nnz, int64_t k, size_t free_
     int64_t gs = (int64_t)(budget / per_group);
     gs = std::min<int64_t>(gs, total);
     gs = std::min<int64_t>(gs, (int64_t)(INT32_MAX / 2) / std::max<int32_t>(n, 1));
+    // one round's work items are counted in 32 bits
+    gs = std::min<int64_t>(gs, (int64_t)INT32_MAX /
+                                   ((int64_t)n + (int64_t)extra_items_per_group(nnz)));
     return (int)std::max<int64_t>(gs, 0);
 }
 
