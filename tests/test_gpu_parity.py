@@ -378,6 +378,7 @@ def test_config_grid_sampled_sources():
 def test_config_rmat22_sampled_sources():
     g = gg.config_graph("rmat22")
     G = bc.Graph(g)
-    srcs = gg.config_sources("rmat22", g)[:2]
+    srcs = gg.config_sources("rmat22", g)[:16]
+    print(f"rmat22 n={g.n} nnz={g.nnz} sources={len(srcs)}", flush=True)
     check_bc(g, G, srcs, **LAUNCH["rmat22"])  # the benchmark's launch settings
     check_state(g, G, int(srcs[0]), **LAUNCH["rmat22"])
