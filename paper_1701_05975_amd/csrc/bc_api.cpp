@@ -1135,10 +1135,11 @@ bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev
         if (tail != head && g_new->nnz - g_old->nnz != dn)
             throw bc_error(BC_E_INVAL, "arc counts %lld -> %lld do not match the change",
                            (long long)g_old->nnz, (long long)g_new->nnz);
-        if (affected)
-            *affected = 0;
-        if (tail == head)
-            return; // a self-loop lies on no shortest path
+        if (tail == head) {
+            if (affected)
+                *affected = 0; // a self-loop lies on no shortest path
+            return;
+        }
         // dist(s, tail) and dist(s, head) for every s: single-source passes from
         // tail and head on the reversed graph (an undirected graph is its own)
         bc_graph *gd = g_old->directed ? g_rev : g_old;
@@ -1177,22 +1178,30 @@ bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev
         int k = 0;
         hip_check(hipMemcpyAsync(&k, cnt.p, 4, hipMemcpyDeviceToHost, r.stream), "count");
         hip_check(hipStreamSynchronize(r.stream), "synchronize");
-        if (affected_dev && k > 0) {
-            hip_check(hipMemcpyAsync(affected_dev, list.p, (size_t)k * 4,
-                                     hipMemcpyDeviceToDevice, r.stream),
-                      "copy affected sources");
-            hip_check(hipStreamSynchronize(r.stream), "synchronize");
-        }
-        if (affected)
-            *affected = k;
-        if (k == 0)
+        // the outputs are written once everything else has succeeded
+        auto finish = [&]() {
+            if (affected_dev && k > 0) {
+                hip_check(hipMemcpyAsync(affected_dev, list.p, (size_t)k * 4,
+                                         hipMemcpyDeviceToDevice, r.stream),
+                          "copy affected sources");
+                hip_check(hipStreamSynchronize(r.stream), "synchronize");
+            }
+            if (affected)
+                *affected = k;
+        };
+        if (k == 0) {
+            finish();
             return;
+        }
         if (2 * (int64_t)k > (int64_t)n) {
             // replacing k sources costs 2k source passes: more than running
             // every source of the new graph once
             const ResolvedOptions rn = resolve_options(g_new, opt, n);
-            hip_check(launch_iota((int32_t *)list.p, n, rn.stream), "source list");
-            compute_device(g_new, (const int32_t *)list.p, nullptr, n, opt, bc_dev, nullptr);
+            DevBuf all;
+            all.alloc((size_t)n * 4);
+            hip_check(launch_iota((int32_t *)all.p, n, rn.stream), "source list");
+            compute_device(g_new, (const int32_t *)all.p, nullptr, n, opt, bc_dev, nullptr);
+            finish();
             return;
         }
         // the affected sources' dependencies before and after the change
@@ -1206,6 +1215,7 @@ bc_status bc_update_arc_device(bc_graph *g_old, bc_graph *g_new, bc_graph *g_rev
         hip_check(launch_dynamic_apply(bc_dev, (const double *)before.p, after, n, rn.stream),
                   "apply");
         hip_check(hipStreamSynchronize(rn.stream), "synchronize");
+        finish();
     });
 }
 
