@@ -28,6 +28,22 @@ template <class T> T *carve(char *&p, size_t count)
     return r;
 }
 
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventPair()
+    {
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+    }
+    ~EventPair()
+    {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+    }
+};
+
 struct Staging {
     IlCtl *host = nullptr; // pinned: [0] read back, [1] written to the device
     Staging() { hip_check(hipHostMalloc((void **)&host, 2 * sizeof(IlCtl)), "hipHostMalloc"); }
@@ -57,10 +73,8 @@ void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_d
     const int32_t n = g->n;
     reset_device_counters(g, st);
     hip_check(launch_fill_u64((unsigned long long *)bc_dev, (size_t)n, 0ull, st), "zero");
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "event");
-    hip_check(hipEventCreate(&e1), "event");
-    hip_check(hipEventRecord(e0, st), "event");
+    EventPair ev;
+    hip_check(hipEventRecord(ev.e0, st), "event");
     uint64_t rounds = 0, bands = 0, reached = 0;
     if (k > 0) {
         size_t free_b = 0, total_b = 0;
@@ -192,11 +206,9 @@ void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_d
             rounds += steps;
         }
     }
-    hip_check(hipEventRecord(e1, st), "event");
+    hip_check(hipEventRecord(ev.e1, st), "event");
     read_device_counters(g, st, cnt);
-    hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    hip_check(hipEventElapsedTime(&ms, ev.e0, ev.e1), "event time");
     cnt.stats.reached = reached;
     cnt.stats.iterations = rounds;
     cnt.stats.bands = bands;
