@@ -7,6 +7,7 @@ from .oracle import (  # noqa: F401
     OracleError,
     SigmaOverflow,
     build,
+    host_threads,
     oracle_bc,
     oracle_bc_edges,
     oracle_changed_sources,

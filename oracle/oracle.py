@@ -36,13 +36,23 @@ def build(force: bool = True, extra_flags: tuple[str, ...] = (), src: str | None
     out = out or lib_path
     if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
         return out
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", *extra_flags, src,
-           "-o", out]
+    # no contraction of a product and a sum into one fused operation: every
+    # term and sum is rounded as written
+    cmd = ["gcc", "-O3", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared", "-pthread",
+           *extra_flags, src, "-o", out]
     subprocess.run(cmd, check=True)
     return out
 
 
 _LIB = None
+
+
+def host_threads() -> int:
+    """Every host core this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
 
 
 def _lib(path: str | None = None):
@@ -89,7 +99,7 @@ def oracle_bc(g, sources, threads: int | None = None, lib: str | None = None) ->
     bc = np.zeros(max(g.n, 1), dtype=np.float64)
     bad = ctypes.c_int64(-1)
     if threads is None:
-        threads = min(os.cpu_count() or 1, 16)
+        threads = host_threads()
     rc = L.oracle_bc(g.n, col.shape[0], _ptr(rp), _ptr(col), _ptr(w), _ptr(src), src.shape[0],
                      threads, _ptr(bc), ctypes.byref(bad))
     if rc == 1:
@@ -108,7 +118,7 @@ def oracle_bc_edges(g, sources, threads: int | None = None, lib: str | None = No
     ebc = np.zeros(max(col.shape[0], 1), dtype=np.float64)
     bad = ctypes.c_int64(-1)
     if threads is None:
-        threads = min(os.cpu_count() or 1, 16)
+        threads = host_threads()
     rc = L.oracle_bc_edges(g.n, col.shape[0], _ptr(rp), _ptr(col), _ptr(w), _ptr(src),
                            src.shape[0], threads, _ptr(bc), _ptr(ebc), ctypes.byref(bad))
     if rc == 1:

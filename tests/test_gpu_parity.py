@@ -14,6 +14,7 @@ import pytest
 import oracle
 from paper_1701_05975_amd import bc, graphgen as gg
 from paper_1701_05975_amd.launch import LAUNCH
+from oracle_cache import cached_oracle_bc
 
 pytestmark = pytest.mark.gpu
 
@@ -364,21 +365,60 @@ def test_config_ba100k_full_launch_linearity():
         check_state(g, G, s, **opts)
 
 
-def test_config_grid_sampled_sources():
+def spread(sources, count: int = 8):
+    """count sources spread evenly over a source list (first and last included)."""
+    idx = np.linspace(0, len(sources) - 1, count).round().astype(int)
+    return [int(sources[i]) for i in idx]
+
+
+def check_states(g, G, sources, **opts):
+    """check_state for several sources; the oracle's single-source runs go to
+    a thread pool (the ctypes calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=min(len(sources), oracle.host_threads())) as ex:
+        want = list(ex.map(lambda s: oracle.oracle_source_state(g, s), sources))
+    for s, (od, osg, odl, _) in zip(sources, want):
+        d, sg, dl = G.source_state(s, **opts)
+        od32 = np.where(od == INF64, INT32_MAX, od).astype(np.int32)
+        assert np.array_equal(d, od32), (s, np.nonzero(d != od32)[0][:10])
+        assert np.array_equal(sg, osg), (s, np.nonzero(sg != osg)[0][:10])
+        rel_close(dl, odl, 1e-12)
+
+
+def test_config_grid1000_full_source_list():
+    """All 1024 sources of the grid workload in the benchmark's launch settings
+    (256 sources in flight, so every slab of the launch is exercised) against
+    the oracle's exact betweenness over the same list; distances and counts
+    bit-exact and dependencies at 1e-12 on 8 sources spread over the list."""
     g = gg.config_graph("grid1000")
+    srcs = gg.config_sources("grid1000", g)
+    assert len(srcs) == 1024
+    want = cached_oracle_bc(g, srcs, label="grid1000")
     G = bc.Graph(g)
-    srcs = gg.config_sources("grid1000", g)[:16]
-    check_bc(g, G, srcs, **LAUNCH["grid1000"])  # the benchmark's launch settings
-    check_bc(g, G, srcs)
-    for s in srcs[:2]:
-        check_state(g, G, int(s), **LAUNCH["grid1000"])
+    got, st = G.bc(srcs, **LAUNCH["grid1000"])
+    assert st["batch"] == LAUNCH["grid1000"]["batch"] and st["sources"] == 1024
+    rel_close(got, want, 1e-9)
+    check_states(g, G, spread(srcs), **LAUNCH["grid1000"])
+    # default options on a prefix of the list
+    check_bc(g, G, srcs[:16])
+    G.close()
 
 
 @pytest.mark.slow
-def test_config_rmat22_sampled_sources():
+def test_config_rmat22_full_source_list():
+    """All 1024 sources of the R-MAT scale-22 workload in the benchmark's launch
+    settings (as many sources in flight as the launch holds) against the
+    oracle's exact betweenness over the same list; distances and counts
+    bit-exact and dependencies at 1e-12 on 8 sources spread over the list."""
     g = gg.config_graph("rmat22")
-    G = bc.Graph(g)
-    srcs = gg.config_sources("rmat22", g)[:16]
+    srcs = gg.config_sources("rmat22", g)
+    assert len(srcs) == 1024
     print(f"rmat22 n={g.n} nnz={g.nnz} sources={len(srcs)}", flush=True)
-    check_bc(g, G, srcs, **LAUNCH["rmat22"])  # the benchmark's launch settings
-    check_state(g, G, int(srcs[0]), **LAUNCH["rmat22"])
+    want = cached_oracle_bc(g, srcs, label="rmat22")
+    G = bc.Graph(g)
+    got, st = G.bc(srcs, **LAUNCH["rmat22"])
+    assert st["sources"] == 1024 and st["batch"] > 64
+    rel_close(got, want, 1e-9)
+    check_states(g, G, spread(srcs), **LAUNCH["rmat22"])
+    G.close()
