@@ -85,6 +85,30 @@ typedef struct bc_result bc_result;
 bc_status bc_create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                           const int32_t *w, uint32_t flags, bc_graph **out);
 
+/*
+ * bc_create_graph_device -- bc_create_graph for a CSR already in device memory
+ * (for example the data pointers of torch tensors).
+ *
+ * row_ptr_dev[n+1] (int64), col_dev[nnz] and w_dev[nnz] (int32) are device
+ * arrays of the current device with the meaning and rules of bc_create_graph
+ * (CSR plus a parallel weight array, Sec. 3.1; undirected graphs must be
+ * symmetric, Sec. 2.1).  Validation, renumbering, packing, the transpose of a
+ * directed graph and the symmetry check of an undirected one all run on the
+ * device, on `stream` (a hipStream_t; NULL = the new graph's own stream), so
+ * the work is ordered after whatever the caller queued there before.  The
+ * resulting graph has the same device layout as bc_create_graph builds from
+ * the same arrays.  The arrays are only read, stay owned by the caller and may
+ * be reused once the call returns (it waits for its device work).
+ *
+ * Errors: as bc_create_graph (BC_E_GRAPH, BC_E_WEIGHT and BC_E_DIST_OVERFLOW
+ * come from the device checks, with the first offending row or arc named in
+ * bc_last_error).  Temporary device memory of about 40 bytes per arc is used
+ * during the call.
+ */
+bc_status bc_create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr_dev,
+                                 const int32_t *col_dev, const int32_t *w_dev, uint32_t flags,
+                                 void *stream, bc_graph **out);
+
 /* Release a graph and every device buffer cached on it.  NULL is accepted. */
 bc_status bc_destroy_graph(bc_graph *g);
 
@@ -154,6 +178,18 @@ typedef struct {
                              graphs renumbered by in-degree, else 32), 16 or 32.  With 16 the
                              cache holds twice the vertices; distances of 65535 and more of
                              those vertices are kept in device memory instead */
+    /* Degree tiers of the adaptive frontier expansion (virtual_warp = 0; the
+       degree-aware thread mapping of Sec. 3.4 on 64-lane wavefronts).  A queued
+       vertex with d out-arcs is expanded by one lane if d <= expand_lane_deg, by a
+       group of 8 lanes if d <= wave_max_deg, else by one whole wave; in the
+       batched form a vertex with d > wg_min_deg is expanded by the whole
+       workgroup after the pass.  The count pass hands vertices with more than
+       wave_max_deg in-arcs to a whole wave.  0 = default (8, 64, 512); a
+       threshold below the one before it is raised to it.  The plain form has no
+       workgroup tier; the interleaved form uses none of them. */
+    int32_t expand_lane_deg;
+    int32_t wave_max_deg;
+    int32_t wg_min_deg;
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -175,8 +211,9 @@ typedef struct {
     int64_t phase_ticks[5];   /* batched form: device clock ticks summed over workgroups spent
                                  in initialisation, frontier expansion, count rounds,
                                  dependency rounds and far-pile splits */
+    /* the settings the computation ran with (defaults and autotuned values filled in) */
     int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode,
-        virtual_warp, node_parallel, lds_bits;
+        virtual_warp, node_parallel, lds_bits, expand_lane_deg, wave_max_deg, wg_min_deg;
 } bc_stats;
 
 /*
@@ -239,10 +276,21 @@ bc_status bc_destroy_result(bc_result *r);
 /*
  * bc_source_state -- full per-vertex state of one source, for checking.
  *
- * Runs source s alone with the given options and copies to host arrays of n
- * elements: d (INT32_MAX when unreachable), sigma (0 when unreachable) and
- * delta (dependency delta_s(v); 0 when unreachable; delta_s(s) equals the
- * number of reached vertices minus one).  Any output pointer may be NULL.
+ * Runs source s alone with the given options (batched or plain form; batch
+ * and autotune are ignored) and copies to host arrays of n elements, in the
+ * caller's vertex ids:
+ *   d[v]     -- the shortest distance d(s, v) of the forward pass (Sec. 2.2;
+ *               Alg. 1 initialises it, Alg. 2 relaxes it), INT32_MAX when v
+ *               is unreachable;
+ *   sigma[v] -- the number of shortest s-v paths, counted by Alg. 2's rule
+ *               (a strictly shorter distance replaces the count, an equal one
+ *               adds to it), 0 when unreachable;
+ *   delta[v] -- the dependency delta_s(v) of the Sec. 2.1 recursion as Alg. 3
+ *               accumulates it, 0 when unreachable; delta_s(s) equals the
+ *               number of reached vertices minus one.
+ * Any output pointer may be NULL.  Errors: BC_E_INVAL (null graph, s out of
+ * range, BC_MODE_INTERLEAVED), BC_E_SIGMA_OVERFLOW, BC_E_NOMEM, BC_E_DEVICE;
+ * the outputs are then not written.
  */
 bc_status bc_source_state(bc_graph *g, int32_t s, const bc_options *opt, int32_t *d,
                           uint64_t *sigma, double *delta);

@@ -54,7 +54,9 @@ class bc_options(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("accumulate", ctypes.c_int32),
                 ("lds_vertices", ctypes.c_int32), ("dep_mode", ctypes.c_int32),
                 ("virtual_warp", ctypes.c_int32), ("node_parallel", ctypes.c_int32),
-                ("lds_bits", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("lds_bits", ctypes.c_int32), ("expand_lane_deg", ctypes.c_int32),
+                ("wave_max_deg", ctypes.c_int32), ("wg_min_deg", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class bc_stats(ctypes.Structure):
@@ -70,7 +72,9 @@ class bc_stats(ctypes.Structure):
                 ("lane_max_deg", ctypes.c_int32), ("wg_threads", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
                 ("dep_mode", ctypes.c_int32), ("virtual_warp", ctypes.c_int32),
-                ("node_parallel", ctypes.c_int32), ("lds_bits", ctypes.c_int32)]
+                ("node_parallel", ctypes.c_int32), ("lds_bits", ctypes.c_int32),
+                ("expand_lane_deg", ctypes.c_int32), ("wave_max_deg", ctypes.c_int32),
+                ("wg_min_deg", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -119,6 +123,7 @@ def _load():
     i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     sig = {
         "bc_create_graph": ([i32, i64, P, P, P, u32, ctypes.POINTER(P)], ctypes.c_int),
+        "bc_create_graph_device": ([i32, i64, P, P, P, u32, P, ctypes.POINTER(P)], ctypes.c_int),
         "bc_destroy_graph": ([P], ctypes.c_int),
         "bc_get_graph_info": ([P, ctypes.POINTER(bc_graph_info)], ctypes.c_int),
         "bc_compute": ([P, P, i64, ctypes.POINTER(bc_options), ctypes.POINTER(P)], ctypes.c_int),
@@ -168,7 +173,7 @@ def _ptr(a: np.ndarray):
 
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
                  accumulate=0, lds_vertices=0, dep_mode=0, virtual_warp=0, node_parallel=0,
-                 lds_bits=0,
+                 lds_bits=0, expand_lane_deg=0, wave_max_deg=0, wg_min_deg=0,
                  stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
@@ -178,6 +183,9 @@ def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotun
     o.virtual_warp = virtual_warp
     o.node_parallel = node_parallel
     o.lds_bits = lds_bits
+    o.expand_lane_deg = expand_lane_deg
+    o.wave_max_deg = wave_max_deg
+    o.wg_min_deg = wg_min_deg
     o.stream = stream
     return o
 
@@ -191,6 +199,17 @@ def bc_create_graph(n: int, row_ptr, col, w, flags: int = 0) -> ctypes.c_void_p:
     out = ctypes.c_void_p()
     _check(_lib.bc_create_graph(int(n), int(c.shape[0]), _ptr(rp), _ptr(c), _ptr(ww),
                                 int(flags), ctypes.byref(out)))
+    return out
+
+
+def bc_create_graph_device(n: int, nnz: int, row_ptr_dev_ptr: int, col_dev_ptr: int,
+                           w_dev_ptr: int, flags: int = 0, stream=None) -> ctypes.c_void_p:
+    """Graph from device arrays (int64 row offsets, int32 heads and weights)."""
+    out = ctypes.c_void_p()
+    _check(_lib.bc_create_graph_device(int(n), int(nnz), ctypes.c_void_p(row_ptr_dev_ptr),
+                                       ctypes.c_void_p(col_dev_ptr or None),
+                                       ctypes.c_void_p(w_dev_ptr or None), int(flags),
+                                       ctypes.c_void_p(stream or None), ctypes.byref(out)))
     return out
 
 
@@ -315,6 +334,22 @@ class Graph:
         flags = (BC_DIRECTED if csr.directed else 0) | (BC_KEEP_ORDER if keep_order else 0)
         flags |= BC_EDGE_BC if edges else 0
         self.handle = bc_create_graph(csr.n, csr.row_ptr, csr.col, csr.w, flags)
+
+    @classmethod
+    def from_device(cls, csr, row_ptr_t, col_t, w_t, keep_order: bool = False,
+                    edges: bool = False, stream=None) -> "Graph":
+        """Graph built by bc_create_graph_device from device tensors (int64 row
+        offsets, int32 heads, int32 weights) holding the CSR of `csr`."""
+        self = cls.__new__(cls)
+        self.n = int(csr.n)
+        self.m = int(csr.m)
+        self.csr = csr
+        flags = (BC_DIRECTED if csr.directed else 0) | (BC_KEEP_ORDER if keep_order else 0)
+        flags |= BC_EDGE_BC if edges else 0
+        self.handle = None
+        self.handle = bc_create_graph_device(csr.n, int(col_t.numel()), row_ptr_t.data_ptr(),
+                                             col_t.data_ptr(), w_t.data_ptr(), flags, stream)
+        return self
 
     def info(self) -> dict:
         return bc_get_graph_info(self.handle)

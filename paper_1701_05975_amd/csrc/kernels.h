@@ -21,14 +21,16 @@ struct BatchArgs {
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
     int32_t lds16;                // LDS entries are 16-bit (65535 = kept in the slab)
-    int32_t hubs;                 // the graph has vertices of more than BC_HUB_DEG arcs
+    int32_t hubs;                 // the graph has vertices of more than wg_deg arcs
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
     int32_t vw;                   // expansion: 0 adaptive lane/wave, else lanes per vertex
     int32_t node_parallel;        // expansion scans every vertex instead of the queue
     double *ebc;                  // optional edge betweenness output (caller arc order)
     const uint32_t *emap;         // in-row position -> caller arc index
     uint32_t delta;               // band width
-    int lane_max;
+    int lane_max;                 // count/dependency passes: lane up to this many arcs
+    uint32_t lane_deg, wave_deg;  // expansion tiers: lane / group of lanes / wave by degree
+    uint32_t wg_deg;              // expansion: more arcs than this -> the whole workgroup
     DevStats *stats;
     unsigned long long *err;      // [0] error bits, [1] first overflowing source index
 };
@@ -59,6 +61,7 @@ struct PlainArgs {
     double *bc_out;
     uint32_t delta;
     int lane_max;
+    uint32_t lane_deg, wave_deg;  // expansion tiers, as in BatchArgs
     DevStats *stats;
     unsigned long long *err;
 };
@@ -88,5 +91,3 @@ hipError_t launch_dynamic_affected(const int32_t *dt, const int32_t *dh, int n, 
 hipError_t launch_iota(int32_t *list, int n, hipStream_t st);
 hipError_t launch_dynamic_apply(double *bc, const double *before, const double *after, int n,
                                 hipStream_t st);
-hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
-                                    hipStream_t st);

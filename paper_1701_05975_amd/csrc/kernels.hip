@@ -92,6 +92,7 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
         rc.perm = ATOMIC_BC ? a.perm : nullptr;
         rc.keys = a.ebc == nullptr;
         rc.band_gen = C.band_gen;
+        rc.wave_deg = a.wave_deg;
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE, RECORD>(g, S, rc, st_arcs, st_dag);
         else
@@ -261,6 +262,9 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ec.huge_q = hubs ? C.huge_q : nullptr;
                 ec.huge_cnt = &C.huge_cnt;
                 ec.keys = a.ebc == nullptr;
+                ec.lane_deg = a.lane_deg;
+                ec.wave_deg = a.wave_deg;
+                ec.wg_deg = a.wg_deg;
                 uint32_t fmin = BC_INF, omin = BC_INF;
                 expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, omin, st_imp);
                 if (hubs) {
@@ -692,6 +696,9 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.huge_q = nullptr; // a hub is one wave's work here (the grid is the team)
         ec.huge_cnt = nullptr;
         ec.keys = 0;
+        ec.lane_deg = a.lane_deg;
+        ec.wave_deg = a.wave_deg;
+        ec.wg_deg = BC_INF;
         uint32_t fmin = BC_INF, omin = BC_INF;
         uint64_t imp = 0;
         expand_pass<PACKED, AG_SCOPE>(g, S, ec, fmin, omin, imp);
@@ -744,6 +751,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.perm = a.perm;
         rc.keys = 0; // the plain form records no predecessor keys
         rc.band_gen = 0;
+        rc.wave_deg = a.wave_deg;
         if (phase == PH_SIGMA) {
             uint64_t arcs = 0, dag = 0;
             sigma_round<PACKED, AG_SCOPE, false>(g, S, rc, arcs, dag);
@@ -963,24 +971,6 @@ __global__ void k_dynamic_apply(double *bc, const double *before, const double *
         bc[v] += after[v] - before[v];
 }
 
-// Minimum outgoing weight per vertex (Delta_node of Sec. 3.2; INT32_MAX when
-// the vertex has no arcs) and the out-degree.
-template <bool PACKED>
-__global__ void k_graph_vertex_info(DevGraph g, int32_t *dnode, int32_t *deg)
-{
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
-        const uint32_t b = g.row[v], e = g.row[v + 1];
-        uint32_t m = BC_INF;
-        for (uint32_t j = b; j < e; ++j) {
-            uint32_t u, w;
-            arc_at<PACKED>(g.arc, g.wt, j, g.wshift, g.wmask, u, w);
-            m = w < m ? w : m;
-        }
-        dnode[v] = (int32_t)m;
-        deg[v] = (int32_t)(e - b);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
@@ -1147,23 +1137,6 @@ hipError_t launch_export_state(char *slab_base, const SlabLayout &L, int slot, i
         blocks = 1;
     hipLaunchKernelGGL(k_export_state, dim3(blocks), dim3(256), 0, st, slab_base, L, slot, n, d,
                        sigma, delta, perm);
-    return hipGetLastError();
-}
-
-hipError_t launch_graph_vertex_info(const DevGraph &g, bool packed, int32_t *dnode, int32_t *deg,
-                                    hipStream_t st)
-{
-    int blocks = (g.n + 255) / 256;
-    if (blocks > 4096)
-        blocks = 4096;
-    if (blocks < 1)
-        blocks = 1;
-    if (packed)
-        hipLaunchKernelGGL(k_graph_vertex_info<true>, dim3(blocks), dim3(256), 0, st, g, dnode,
-                           deg);
-    else
-        hipLaunchKernelGGL(k_graph_vertex_info<false>, dim3(blocks), dim3(256), 0, st, g, dnode,
-                           deg);
     return hipGetLastError();
 }
 

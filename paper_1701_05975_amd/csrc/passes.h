@@ -130,6 +130,9 @@ struct ExpandCtx {
     int32_t *huge_q;      // optional: vertices with more than EXPAND_WG_DEG arcs are listed
     int *huge_cnt;        // here for the whole workgroup to expand after the pass
     int keys;             // record each vertex's (distance, predecessor) key and ties
+    uint32_t lane_deg;    // adaptive mapping: at most this many arcs -> one lane,
+    uint32_t wave_deg;    // at most this many -> a group of EXPAND_GROUP lanes, more -> a wave,
+    uint32_t wg_deg;      // more than this (batched, huge_q set) -> the whole workgroup
 };
 
 // Predecessor keys (batched form).  While distances are being found, the
@@ -157,19 +160,18 @@ __device__ __forceinline__ uint64_t *key_ptr(const Slab &S, int32_t v)
 #endif
 
 // Adaptive expansion (Sec. 3.4's degree-aware mapping, three tiers): a vertex
-// with at most EXPAND_GROUP arcs is walked by one lane, one with at most
-// EXPAND_WAVE_DEG by a group of EXPAND_GROUP lanes, a larger one by the wave.
+// with at most lane_deg arcs is walked by one lane, one with at most wave_deg
+// by a group of EXPAND_GROUP lanes, a larger one by the wave.  The thresholds
+// are run-time values (BC_DEF_LANE_DEG and BC_DEF_WAVE_DEG by default); the
+// group width is fixed.
 #ifndef EXPAND_GROUP
 #define EXPAND_GROUP 8
 #endif
-#ifndef EXPAND_WAVE_DEG
-#define EXPAND_WAVE_DEG 64
-#endif
-// Fourth tier (batched form): a vertex with more than EXPAND_WG_DEG arcs is
-// expanded by every thread of the workgroup after the pass, so that one hub
-// does not keep one wave busy while the others wait at the barrier.  The list
-// holds EXPAND_WG_CAP vertices; further ones take the wave path.
-#define EXPAND_WG_DEG BC_HUB_DEG
+// Fourth tier (batched form): a vertex with more than wg_deg arcs (default
+// BC_HUB_DEG) is expanded by every thread of the workgroup after the pass, so
+// that one hub does not keep one wave busy while the others wait at the
+// barrier.  The list holds EXPAND_WG_CAP vertices; further ones take the wave
+// path.
 #define EXPAND_WG_CAP 256
 
 template <int SCOPE>
@@ -282,11 +284,11 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             }
         }
         const uint32_t deg = end - beg;
-        const bool light = valid && deg <= (uint32_t)EXPAND_GROUP;
-        const bool mid = valid && deg > (uint32_t)EXPAND_GROUP && deg <= (uint32_t)EXPAND_WAVE_DEG;
-        bool heavy = valid && deg > (uint32_t)EXPAND_WAVE_DEG;
+        const bool light = valid && deg <= c.lane_deg;
+        const bool mid = valid && deg > c.lane_deg && deg <= c.wave_deg;
+        bool heavy = valid && deg > c.wave_deg;
         if (c.huge_q) {
-            const bool huge = heavy && deg > (uint32_t)EXPAND_WG_DEG;
+            const bool huge = heavy && deg > c.wg_deg;
             const int k = wave_alloc(c.huge_cnt, huge);
             if (huge && k < EXPAND_WG_CAP) {
                 c.huge_q[k] = v;
@@ -495,6 +497,8 @@ struct RoundCtx {
     int keys;                // predecessor keys were recorded (count pass shortcut)
     int32_t band_gen;        // queue tag of the band's first pass: a vertex with a tag at
                              // least this is a member of the band being counted
+    uint32_t wave_deg;       // more in-arcs than this: the whole wave (else a group of
+                             // EXPAND_GROUP lanes above lane_max, one lane below)
 };
 
 __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
@@ -587,7 +591,7 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
             }
         }
         const uint32_t deg = end - beg;
-        const bool heavy = valid && !is_src && !keyed && deg > (uint32_t)EXPAND_WAVE_DEG;
+        const bool heavy = valid && !is_src && !keyed && deg > c.wave_deg;
         const bool mid = valid && !is_src && !keyed && !heavy && deg > (uint32_t)c.lane_max;
         if (valid && !is_src && !keyed && !heavy && !mid) {
             const uint32_t dv = dist_get(S, v);

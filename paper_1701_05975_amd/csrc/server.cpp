@@ -177,7 +177,7 @@ class HipExec {
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
         a.lds16 = c->lds16;
-        a.hubs = g->maxdeg > BC_HUB_DEG;
+        set_tier_args(g, tier_for(g, 0), tier_for(g, 1), tier_for(g, 2), a);
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.ebc = nullptr;
         a.emap = nullptr;
@@ -271,6 +271,20 @@ class HipExec {
         if (opts_.compute.lane_max_deg)
             return opts_.compute.lane_max_deg;
         return g->tuned.valid ? g->tuned.lane_max : 32;
+    }
+    // expansion degree tiers: 0 lane, 1 group of lanes, 2 workgroup
+    int tier_for(bc_graph *g, int which) const
+    {
+        const bc_options &o = opts_.compute;
+        const int given[3] = {o.expand_lane_deg, o.wave_max_deg, o.wg_min_deg};
+        const int tuned[3] = {g->tuned.lane_deg, g->tuned.wave_deg, g->tuned.wg_deg};
+        const int def[3] = {BC_DEF_LANE_DEG, BC_DEF_WAVE_DEG, BC_HUB_DEG};
+        int t[3];
+        for (int i = 0; i < 3; ++i)
+            t[i] = given[i] > 0 ? given[i] : (g->tuned.valid && tuned[i] > 0 ? tuned[i] : def[i]);
+        t[1] = std::max(t[1], t[0]);
+        t[2] = std::max(t[2], t[1]);
+        return t[which];
     }
     int dep_mode_for(bc_graph *g) const
     {

@@ -6,8 +6,12 @@
 
 #define BC_INF 0x7fffffffu
 #define WAVE 64
-// Batched expansion: vertices with more arcs than this are expanded by the
-// whole workgroup (only graphs that have such a vertex pay for the step).
+// Default degree thresholds of the adaptive mapping: at most BC_DEF_LANE_DEG
+// arcs -> one lane, at most BC_DEF_WAVE_DEG -> a group of lanes, more -> a
+// wave; in the batched expansion more than BC_HUB_DEG -> the whole workgroup
+// (only graphs that have such a vertex pay for the step).
+#define BC_DEF_LANE_DEG 8
+#define BC_DEF_WAVE_DEG 64
 #define BC_HUB_DEG 512
 
 // ---------------------------------------------------------------------------
