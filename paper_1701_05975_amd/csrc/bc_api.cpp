@@ -232,22 +232,14 @@ static void upload_arcs(bc_graph *g, int32_t n, const int64_t *row_ptr, const in
     }
 }
 
+static void check_create_args(int32_t n, int64_t nnz, const void *row_ptr, const void *col,
+                              const void *w, uint32_t flags, bc_graph **out);
+static void init_graph_runtime(bc_graph *g);
+
 static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *w, uint32_t flags, bc_graph **out)
 {
-    if (!out)
-        throw bc_error(BC_E_INVAL, "out is NULL");
-    if (n < 1)
-        throw bc_error(BC_E_INVAL, "n must be >= 1 (got %d)", n);
-    if (nnz < 0)
-        throw bc_error(BC_E_INVAL, "nnz must be >= 0");
-    if (nnz >= (int64_t)UINT32_MAX)
-        throw bc_error(BC_E_INVAL, "nnz must be below 2^32 - 1");
-    if (!row_ptr || (nnz > 0 && (!col || !w)))
-        throw bc_error(BC_E_INVAL, "null CSR array");
-    const uint32_t known = BC_DIRECTED | BC_KEEP_ORDER | BC_EDGE_BC;
-    if (flags & ~known)
-        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~known);
+    check_create_args(n, nnz, row_ptr, col, w, flags, out);
     if (row_ptr[0] != 0 || row_ptr[n] != nnz)
         throw bc_error(BC_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
     int64_t maxdeg = 0;
@@ -280,6 +272,7 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
 
     ensure_device();
     std::unique_ptr<bc_graph> g(new bc_graph());
+    init_graph_runtime(g.get());
     g->n = n;
     g->nnz = nnz;
     g->directed = directed;
@@ -299,14 +292,6 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
     for (int64_t e = 0; e < nnz; ++e)
         wsum += w[e];
     g->wmean = nnz ? wsum / (double)nnz : 1.0;
-
-    hip_check(hipGetDevice(&g->device), "hipGetDevice");
-    hipDeviceProp_t prop;
-    hip_check(hipGetDeviceProperties(&prop, g->device), "hipGetDeviceProperties");
-    g->num_cus = prop.multiProcessorCount;
-    hip_check(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
-    hip_check(hipEventCreate(&g->ev_k0), "hipEventCreate");
-    hip_check(hipEventCreate(&g->ev_k1), "hipEventCreate");
 
     // Renumber skewed graphs by decreasing in-degree (ties keep the caller's
     // order): the most frequent arc heads get the lowest ids, whose distances
@@ -394,17 +379,43 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
                   "upload arc map");
     }
     g->edges_ready = want_edges;
-    g->dnode.alloc((size_t)n * sizeof(int32_t));
-    g->deg.alloc((size_t)n * sizeof(int32_t));
-    hip_check(launch_graph_vertex_info(g->view(), g->packed, (int32_t *)g->dnode.p,
-                                       (int32_t *)g->deg.p, g->stream),
-              "vertex info");
+    hip_check(hipStreamSynchronize(g->stream), "graph upload");
+    *out = g.release();
+}
+
+// Argument checks shared by both ingest paths (host and device arrays).
+static void check_create_args(int32_t n, int64_t nnz, const void *row_ptr, const void *col,
+                              const void *w, uint32_t flags, bc_graph **out)
+{
+    if (!out)
+        throw bc_error(BC_E_INVAL, "out is NULL");
+    if (n < 1)
+        throw bc_error(BC_E_INVAL, "n must be >= 1 (got %d)", n);
+    if (nnz < 0)
+        throw bc_error(BC_E_INVAL, "nnz must be >= 0");
+    if (nnz >= (int64_t)UINT32_MAX)
+        throw bc_error(BC_E_INVAL, "nnz must be below 2^32 - 1");
+    if (!row_ptr || (nnz > 0 && (!col || !w)))
+        throw bc_error(BC_E_INVAL, "null CSR array");
+    const uint32_t known = BC_DIRECTED | BC_KEEP_ORDER | BC_EDGE_BC;
+    if (flags & ~known)
+        throw bc_error(BC_E_INVAL, "unknown flag bits 0x%x", flags & ~known);
+}
+
+// Device, stream, timing events and the per-graph counter blocks.
+static void init_graph_runtime(bc_graph *g)
+{
+    hip_check(hipGetDevice(&g->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, g->device), "hipGetDeviceProperties");
+    g->num_cus = prop.multiProcessorCount;
+    hip_check(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreate(&g->ev_k0), "hipEventCreate");
+    hip_check(hipEventCreate(&g->ev_k1), "hipEventCreate");
     g->ctl.alloc(sizeof(DevCounters));
     g->plain_ctl.alloc(sizeof(PlainCtl));
     hip_check(hipHostMalloc((void **)&g->host_counters, sizeof(DevCounters)), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&g->host_plain, sizeof(PlainCtl)), "hipHostMalloc");
-    hip_check(hipStreamSynchronize(g->stream), "graph upload");
-    *out = g.release();
 }
 
 DevGraph bc_graph::view() const
@@ -579,6 +590,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "lds_bits must be 0, 16 or 32");
     if (o.node_parallel < 0 || o.node_parallel > 1)
         throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
+    if (o.expand_lane_deg < 0 || o.wave_max_deg < 0 || o.wg_min_deg < 0)
+        throw bc_error(BC_E_INVAL, "negative degree threshold");
     r.mode = o.mode == BC_MODE_PLAIN || o.mode == BC_MODE_INTERLEAVED ? o.mode : BC_MODE_BATCHED;
     r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
     r.wg_threads = o.wg_threads ? o.wg_threads : 256;
@@ -595,6 +608,10 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.dep_mode = o.dep_mode ? o.dep_mode : 1;
     r.vw = o.virtual_warp;
     r.node_parallel = o.node_parallel;
+    // the tiers keep their order: a threshold below the one before it is raised to it
+    r.lane_deg = o.expand_lane_deg ? o.expand_lane_deg : BC_DEF_LANE_DEG;
+    r.wave_deg = std::max(r.lane_deg, o.wave_max_deg ? o.wave_max_deg : BC_DEF_WAVE_DEG);
+    r.wg_deg = std::max(r.wave_deg, o.wg_min_deg ? o.wg_min_deg : BC_HUB_DEG);
     r.il_groups = (int)std::min<int64_t>(((int64_t)o.batch + 63) / 64, INT32_MAX);
     int per_cu = 1;
     r.lds_bits = lds_bits_for(g, o.lds_bits);
@@ -674,6 +691,17 @@ static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters 
     st->dep_mode = r.dep_mode;
     st->virtual_warp = r.vw;
     st->node_parallel = r.node_parallel;
+    st->expand_lane_deg = r.lane_deg;
+    st->wave_max_deg = r.wave_deg;
+    st->wg_min_deg = r.wg_deg;
+}
+
+void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a)
+{
+    a.lane_deg = (uint32_t)lane_deg;
+    a.wave_deg = (uint32_t)wave_deg;
+    a.wg_deg = (uint32_t)wg_deg;
+    a.hubs = g->maxdeg > wg_deg;
 }
 
 static void check_device_errors(const DevCounters &c)
@@ -720,7 +748,7 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         a.perm = g->perm_dev();
         a.H = r.lds_vertices;
         a.lds16 = r.lds_bits == 16;
-        a.hubs = g->maxdeg > BC_HUB_DEG;
+        set_tier_args(g, r.lane_deg, r.wave_deg, r.wg_deg, a);
         a.kahn = r.dep_mode == 1 ? 1 : 0;
         a.vw = r.vw;
         a.node_parallel = r.node_parallel;
@@ -768,6 +796,8 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     a.bc_out = nullptr; // the output travels in the control block
     a.delta = (uint32_t)r.delta;
     a.lane_max = r.lane_max;
+    a.lane_deg = (uint32_t)r.lane_deg;
+    a.wave_deg = (uint32_t)r.wave_deg;
     DevCounters *c = (DevCounters *)g->ctl.p;
     a.stats = &c->stats;
     a.err = c->err;
@@ -786,7 +816,8 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
     // with the same band width and lane threshold.
     const int PLAIN_GRAPH_PAIRS = 32;
     if (!g->plain_exec || g->plain_exec_delta != a.delta || g->plain_exec_lane_max != a.lane_max ||
-        g->plain_exec_vw != a.vw || g->plain_exec_slab != (const void *)a.slab_base) {
+        g->plain_exec_vw != a.vw || g->plain_exec_slab != (const void *)a.slab_base ||
+        g->plain_exec_tiers != (((uint64_t)a.lane_deg << 32) | a.wave_deg)) {
         if (g->plain_exec) {
             (void)hipGraphExecDestroy(g->plain_exec);
             g->plain_exec = nullptr;
@@ -805,6 +836,7 @@ static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_
         g->plain_exec_lane_max = a.lane_max;
         g->plain_exec_vw = a.vw;
         g->plain_exec_slab = (const void *)a.slab_base;
+        g->plain_exec_tiers = ((uint64_t)a.lane_deg << 32) | a.wave_deg;
     }
     const unsigned long long iter_cap = 8ull * (unsigned long long)g->n + 1024ull;
     hipEvent_t e0, e1;
@@ -901,6 +933,21 @@ bc_status bc_create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const 
                           const int32_t *w, uint32_t flags, bc_graph **out)
 {
     return guarded([&] { create_graph(n, nnz, row_ptr, col, w, flags, out); });
+}
+
+bc_status bc_create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr_dev,
+                                 const int32_t *col_dev, const int32_t *w_dev, uint32_t flags,
+                                 void *stream, bc_graph **out)
+{
+    return guarded([&] {
+        check_create_args(n, nnz, row_ptr_dev, col_dev, w_dev, flags, out);
+        ensure_device();
+        std::unique_ptr<bc_graph> g(new bc_graph());
+        init_graph_runtime(g.get());
+        create_graph_device(n, nnz, row_ptr_dev, col_dev, w_dev, flags,
+                            stream ? (hipStream_t)stream : g->stream, g.get());
+        *out = g.release();
+    });
 }
 
 bc_status bc_destroy_graph(bc_graph *g)

@@ -55,6 +55,9 @@ struct ResolvedOptions {
     int lds_bits = 32;    // width of an LDS distance entry (16 or 32)
     int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
     int vw = 0;           // expansion lanes per vertex (0 adaptive)
+    int lane_deg = BC_DEF_LANE_DEG; // adaptive expansion: one lane up to this many arcs,
+    int wave_deg = BC_DEF_WAVE_DEG; // a group of lanes up to this many, a wave above,
+    int wg_deg = BC_HUB_DEG;        // the whole workgroup above this (batched form)
     int node_parallel = 0;
     int il_groups = 0;    // interleaved form: groups of 64 sources per sweep (0 = by memory)
     hipStream_t stream = nullptr;
@@ -63,6 +66,8 @@ struct ResolvedOptions {
 struct TunedOptions {
     bool valid = false;
     int delta = 0, lane_max = 0, wg_threads = 0, dep_mode = 0;
+    int lane_deg = 0, wave_deg = 0, wg_deg = 0;
+    int batch = 0; // sources in flight chosen for the tuning call's source count
     double best_ms_per_source = 0.0;
 };
 
@@ -84,7 +89,6 @@ struct bc_graph {
 
     DevBuf row, arc, wt;    // out-arcs
     DevBuf trow, tarc, twt; // in-arcs (directed graphs only)
-    DevBuf dnode, deg;      // per-vertex minimum out-weight and out-degree
     DevBuf perm, iperm;     // internal -> caller id, caller -> internal id (when renumbered)
     DevBuf emap;            // in-row position -> caller arc index (edge betweenness)
     bool edges_ready = false;
@@ -101,6 +105,7 @@ struct bc_graph {
     uint32_t plain_exec_delta = 0;
     int plain_exec_lane_max = 0;
     int plain_exec_vw = 0;
+    uint64_t plain_exec_tiers = 0;
     const void *plain_exec_slab = nullptr;
 
     Workspace batched, plain;
@@ -135,6 +140,13 @@ void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host
 void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int32_t *src_dev,
               int64_t k);
 void reset_device_counters(bc_graph *g, hipStream_t st);
+// Device-side ingest behind bc_create_graph_device: validates the caller's
+// device CSR and builds g's device layout on stream st (g's runtime fields,
+// stream and counters already set up).
+void create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *w, uint32_t flags, hipStream_t st, bc_graph *g);
+// Degree-tier fields of the batched kernel's arguments.
+void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a);
 void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);
 // Source-interleaved form: groups of 64 sources per sweep for n vertices, nnz
 // arcs, k sources and the given free device bytes (0: not even one fits).

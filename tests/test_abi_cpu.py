@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ["bc_create_graph", "bc_destroy_graph", "bc_compute", "bc_compute_device",
+    for must in ["bc_create_graph", "bc_create_graph_device", "bc_destroy_graph", "bc_compute", "bc_compute_device",
                  "bc_result_bc", "bc_result_device_ptr", "bc_result_stats", "bc_destroy_result",
                  "bc_source_state", "bc_last_error"]:
         assert must in names
