@@ -716,6 +716,44 @@ static void check_device_errors(const DevCounters &c)
                        (long long)c.err[1]);
 }
 
+void launch_batched_pass(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev,
+                         int64_t k, double *bc_dev, char *slab_base, const SlabLayout &L,
+                         int nslabs, double *ebc_dev, hipStream_t st)
+{
+    const bool atomic_bc = r.accumulate == 2;
+    BatchArgs a;
+    a.g = g->view();
+    a.slab_base = slab_base;
+    a.L = L;
+    a.sources = src_dev;
+    a.k = k;
+    DevCounters *c = (DevCounters *)g->ctl.p;
+    a.next_src = &c->next_src;
+    a.bc_out = bc_dev;
+    a.item_out = nullptr;
+    a.item_err = nullptr;
+    a.iperm = g->iperm_dev();
+    a.perm = g->perm_dev();
+    a.H = r.lds_vertices;
+    a.lds16 = r.lds_bits == 16;
+    set_tier_args(g, r.lane_deg, r.wave_deg, r.wg_deg, a);
+    a.kahn = r.dep_mode == 1 ? 1 : 0;
+    a.vw = r.vw;
+    a.node_parallel = r.node_parallel;
+    a.ebc = ebc_dev;
+    a.emap = (const uint32_t *)g->emap.p;
+    a.delta = (uint32_t)r.delta;
+    a.lane_max = r.lane_max;
+    a.stats = &c->stats;
+    a.err = c->err;
+    hip_check(hipEventRecord(g->ev_k0, st), "event");
+    hip_check(launch_batched(a, g->packed, r.wg_threads, atomic_bc, nslabs, st), "batched kernel");
+    hip_check(hipEventRecord(g->ev_k1, st), "event");
+    if (!atomic_bc)
+        hip_check(launch_reduce_partials(slab_base, L, nslabs, g->n, bc_dev, a.perm, st),
+                  "reduce");
+}
+
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
                  double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms, double *ebc_dev)
 {
@@ -728,45 +766,23 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
     if (ebc_dev)
         hip_check(launch_fill_u64((unsigned long long *)ebc_dev, (size_t)g->nnz, 0ull, st),
                   "zero");
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Events {
+        hipEvent_t &a, &b;
+        ~Events()
+        {
+            if (a)
+                (void)hipEventDestroy(a);
+            if (b)
+                (void)hipEventDestroy(b);
+        }
+    } release{e0, e1};
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     hip_check(hipEventRecord(e0, st), "event");
-    if (k > 0) {
-        BatchArgs a;
-        a.g = g->view();
-        a.slab_base = (char *)g->batched.base.p;
-        a.L = g->batched.L;
-        a.sources = src_dev;
-        a.k = k;
-        DevCounters *c = (DevCounters *)g->ctl.p;
-        a.next_src = &c->next_src;
-        a.bc_out = bc_dev;
-        a.item_out = nullptr;
-        a.item_err = nullptr;
-        a.iperm = g->iperm_dev();
-        a.perm = g->perm_dev();
-        a.H = r.lds_vertices;
-        a.lds16 = r.lds_bits == 16;
-        set_tier_args(g, r.lane_deg, r.wave_deg, r.wg_deg, a);
-        a.kahn = r.dep_mode == 1 ? 1 : 0;
-        a.vw = r.vw;
-        a.node_parallel = r.node_parallel;
-        a.ebc = ebc_dev;
-        a.emap = (const uint32_t *)g->emap.p;
-        a.delta = (uint32_t)r.delta;
-        a.lane_max = r.lane_max;
-        a.stats = &c->stats;
-        a.err = c->err;
-        const int nslabs = (int)std::min<int64_t>(r.batch, k);
-        hip_check(hipEventRecord(g->ev_k0, st), "event");
-        hip_check(launch_batched(a, g->packed, r.wg_threads, atomic_bc, nslabs, st),
-                  "batched kernel");
-        hip_check(hipEventRecord(g->ev_k1, st), "event");
-        if (!atomic_bc)
-            hip_check(launch_reduce_partials(a.slab_base, a.L, nslabs, g->n, bc_dev, a.perm, st),
-                      "reduce");
-    }
+    if (k > 0)
+        launch_batched_pass(g, r, src_dev, k, bc_dev, (char *)g->batched.base.p, g->batched.L,
+                            (int)std::min<int64_t>(r.batch, k), ebc_dev, st);
     hip_check(hipEventRecord(e1, st), "event");
     read_device_counters(g, st, cnt);
     hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
@@ -775,8 +791,6 @@ void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, 
         if (k > 0)
             hip_check(hipEventElapsedTime(kernel_ms, g->ev_k0, g->ev_k1), "event time");
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
 }
 
 static void run_plain(bc_graph *g, const ResolvedOptions &r, const int32_t *src_host, int64_t k,

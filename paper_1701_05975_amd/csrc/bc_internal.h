@@ -153,6 +153,12 @@ void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);
 int interleaved_groups_per_sweep(int32_t n, int64_t nnz, int64_t k, size_t free_bytes);
 void run_interleaved(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
                      double *bc_dev, DevCounters &cnt, float &ms);
+// One launch of the batched kernel over nslabs slabs at slab_base (reset,
+// layout L) plus the reduction of their partial sums, with g->ev_k0/ev_k1
+// recorded around the kernel; counters reset and outputs cleared by the caller.
+void launch_batched_pass(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev,
+                         int64_t k, double *bc_dev, char *slab_base, const SlabLayout &L,
+                         int nslabs, double *ebc_dev, hipStream_t st);
 void run_batched(bc_graph *g, const ResolvedOptions &r, const int32_t *src_dev, int64_t k,
                  double *bc_dev, DevCounters &cnt, float &ms, float *kernel_ms,
                  double *ebc_dev = nullptr);
