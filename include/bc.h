@@ -109,7 +109,9 @@ bc_status bc_create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr_
                                  const int32_t *col_dev, const int32_t *w_dev, uint32_t flags,
                                  void *stream, bc_graph **out);
 
-/* Release a graph and every device buffer cached on it.  NULL is accepted. */
+/* Release a graph and every device buffer cached on it.  NULL is accepted.
+   BC_E_BUSY (nothing released) while a live server holds the graph: a server
+   holds every graph submitted to it until bc_server_destroy. */
 bc_status bc_destroy_graph(bc_graph *g);
 
 typedef struct {
@@ -121,6 +123,12 @@ typedef struct {
     int32_t packed_arcs; /* 1 when arc head and weight share one 32-bit word on the device */
     int32_t renumbered;  /* 1 when the device numbering is by decreasing in-degree */
     int64_t device_bytes; /* graph bytes resident on the device */
+    /* the autotuner's cached choice (bc_options.autotune); 0 fields before it ran */
+    int32_t tuned;        /* 1 once a call with autotune set has tuned this graph */
+    int32_t tuned_delta, tuned_wg_threads, tuned_lane_max_deg, tuned_dep_mode;
+    int32_t tuned_expand_lane_deg, tuned_wave_max_deg, tuned_wg_min_deg;
+    int32_t tuned_batch;  /* sources in flight; 0 = the full occupancy of the workgroup size */
+    int64_t tuning_trials; /* candidate settings timed on this graph so far */
 } bc_graph_info;
 
 bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info);
@@ -157,7 +165,11 @@ typedef struct {
                              in-arcs (recorded predecessors) are handled by one lane, larger
                              ones by a whole 64-lane wave */
     int32_t wg_threads;   /* batched: threads per workgroup (256, 512 or 1024) */
-    int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best */
+    int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best:
+                             band width, workgroup size, dependency method, lane_max_deg,
+                             the expansion degree tiers and the sources in flight, each
+                             unless set here, on a prefix of the source list (batched
+                             form); later calls reuse the choice (bc_get_graph_info) */
     int32_t accumulate;   /* 0 = default, 1 = per-slot partial sums + reduction,
                              2 = device-wide FP64 atomic adds into the output */
     int32_t lds_vertices; /* batched: distances of this many highest in-degree vertices are
@@ -398,7 +410,11 @@ bc_status bc_server_create(const bc_server_opts *opts, bc_server **out);
 /*
  * Queue a request: betweenness of graph g over sources[k] (host array, copied;
  * k = 0 allowed).  Returns at once with a ticket.  BC_E_BUSY if the result can
- * never fit the server's budget; BC_E_INVAL for out-of-range sources.
+ * never fit the server's budget; BC_E_INVAL for out-of-range sources.  From
+ * its first request on, the server holds g (bc_destroy_graph returns BC_E_BUSY)
+ * until bc_server_destroy.  If the device memory for g's sweep state cannot be
+ * found, the requests of g waiting for a sweep fail with BC_E_NOMEM (returned
+ * by bc_server_wait) and the server goes on with the other graphs.
  */
 bc_status bc_server_submit(bc_server *sv, bc_graph *g, const int32_t *sources, int64_t k,
                            uint64_t *ticket);

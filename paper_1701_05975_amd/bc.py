@@ -86,7 +86,12 @@ class bc_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("directed", ctypes.c_int32),
                 ("w_max", ctypes.c_int32), ("max_out_degree", ctypes.c_int32),
                 ("packed_arcs", ctypes.c_int32), ("renumbered", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("tuned", ctypes.c_int32),
+                ("tuned_delta", ctypes.c_int32), ("tuned_wg_threads", ctypes.c_int32),
+                ("tuned_lane_max_deg", ctypes.c_int32), ("tuned_dep_mode", ctypes.c_int32),
+                ("tuned_expand_lane_deg", ctypes.c_int32), ("tuned_wave_max_deg", ctypes.c_int32),
+                ("tuned_wg_min_deg", ctypes.c_int32), ("tuned_batch", ctypes.c_int32),
+                ("tuning_trials", ctypes.c_int64)]
 
 
 class bc_server_opts(ctypes.Structure):
@@ -439,10 +444,13 @@ class Server:
     """Owning wrapper of a bc_server handle."""
 
     def __init__(self, **opts):
+        self._graphs = {}  # graphs the server holds until it is closed
         self.handle = bc_server_create(make_server_opts(**opts))
 
     def submit(self, graph: "Graph", sources) -> int:
-        return bc_server_submit(self.handle, graph.handle, sources)
+        t = bc_server_submit(self.handle, graph.handle, sources)
+        self._graphs[graph.handle.value] = graph
+        return t
 
     def wait(self, ticket: int, n: int, timeout_us: int = -1):
         """(bc float64[n], latency ms) of a finished request."""
@@ -459,6 +467,7 @@ class Server:
         if self.handle:
             bc_server_destroy(self.handle)
             self.handle = None
+        self._graphs = {}
 
     def __del__(self):
         try:

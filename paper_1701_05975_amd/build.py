@@ -31,10 +31,17 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, objdir: str) -> str:
+# Host-side sanitizers for a checking build of the library (device code is
+# compiled as usual: each flag applies to the host compilation only).
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host",
+                 "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def _compile(src: str, objdir: str, extra: tuple[str, ...] = ()) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(objdir, src + ".o")
-    cmd = [hipcc(), *COMMON, "-c", path, "-o", obj]
+    cmd = [hipcc(), *COMMON, *extra, "-c", path, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip", *DEVICE]
     else:
@@ -49,21 +56,27 @@ def _compile(src: str, objdir: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, out: str | None = None, objdir: str | None = None,
+          sanitize: bool = False) -> str:
+    """Compiles every source and links the shared library (in-tree by
+    default).  sanitize=True adds the host-side address and undefined-behaviour
+    sanitizers (a checking build, written to `out`)."""
+    out = out or OUT
+    objdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    extra = tuple(HOST_SANITIZE) if sanitize else ()
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, objdir), srcs))
-    tmp = OUT + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        objs = list(ex.map(lambda s: _compile(s, objdir, extra), srcs))
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

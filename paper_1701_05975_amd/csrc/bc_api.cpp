@@ -202,44 +202,47 @@ static bool rows_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col
     return true;
 }
 
-static void upload_arcs(bc_graph *g, int32_t n, const int64_t *row_ptr, const int32_t *col,
-                        const int32_t *w, DevBuf &drow, DevBuf &darc, DevBuf &dwt)
+// Device layout of a graph, built on the host before anything touches the
+// device: row offsets and packed arcs (out-arcs, and in-arcs for directed
+// graphs), the renumbering and the edge map.
+struct HostLayout {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    bool directed = false, packed = false, renumbered = false, edges = false;
+    int32_t wmax = 1, maxdeg = 0;
+    int wbytes = 1;
+    uint32_t wshift = 0, wmask = 0;
+    double avg_deg = 0.0, wmean = 1.0;
+    std::vector<uint32_t> row, arc, trow, tarc;
+    std::vector<int32_t> wt, twt; // only when the arcs are not packed
+    std::vector<int32_t> perm, iperm;
+    std::vector<uint32_t> emap;
+};
+
+// Row offsets and arc words of a CSR (head << wshift | weight - 1 when packed).
+static void pack_csr(const HostLayout &L, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                     const int32_t *w, std::vector<uint32_t> &row, std::vector<uint32_t> &arc,
+                     std::vector<int32_t> &wt)
 {
     const int64_t nnz = row_ptr[n];
-    std::vector<uint32_t> r((size_t)n + 1);
+    row.resize((size_t)n + 1);
     for (int32_t v = 0; v <= n; ++v)
-        r[(size_t)v] = (uint32_t)row_ptr[v];
-    std::vector<uint32_t> a((size_t)nnz);
-    if (g->packed) {
+        row[(size_t)v] = (uint32_t)row_ptr[v];
+    arc.resize((size_t)nnz);
+    if (L.packed) {
         for (int64_t e = 0; e < nnz; ++e)
-            a[(size_t)e] = ((uint32_t)col[e] << g->wshift) | ((uint32_t)(w[e] - 1) & g->wmask);
+            arc[(size_t)e] = ((uint32_t)col[e] << L.wshift) | ((uint32_t)(w[e] - 1) & L.wmask);
     } else {
         for (int64_t e = 0; e < nnz; ++e)
-            a[(size_t)e] = (uint32_t)col[e];
-    }
-    drow.alloc(r.size() * sizeof(uint32_t));
-    hip_check(hipMemcpy(drow.p, r.data(), r.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-              "upload row offsets");
-    if (nnz > 0) {
-        darc.alloc(a.size() * sizeof(uint32_t));
-        hip_check(hipMemcpy(darc.p, a.data(), a.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-                  "upload arcs");
-        if (!g->packed) {
-            dwt.alloc((size_t)nnz * sizeof(int32_t));
-            hip_check(hipMemcpy(dwt.p, w, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice),
-                      "upload weights");
-        }
+            arc[(size_t)e] = (uint32_t)col[e];
+        wt.assign(w, w + nnz);
     }
 }
 
-static void check_create_args(int32_t n, int64_t nnz, const void *row_ptr, const void *col,
-                              const void *w, uint32_t flags, bc_graph **out);
-static void init_graph_runtime(bc_graph *g);
-
-static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
-                         const int32_t *w, uint32_t flags, bc_graph **out)
+// Validation and the whole host-side layout (no device call).
+static void build_host_layout(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                              const int32_t *w, uint32_t flags, HostLayout &L)
 {
-    check_create_args(n, nnz, row_ptr, col, w, flags, out);
     if (row_ptr[0] != 0 || row_ptr[n] != nnz)
         throw bc_error(BC_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
     int64_t maxdeg = 0;
@@ -270,28 +273,25 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
                        "undirected graph is not symmetric (every arc needs a reverse arc of "
                        "equal weight); pass BC_DIRECTED for one-way arcs");
 
-    ensure_device();
-    std::unique_ptr<bc_graph> g(new bc_graph());
-    init_graph_runtime(g.get());
-    g->n = n;
-    g->nnz = nnz;
-    g->directed = directed;
-    g->wmax = wmax;
-    g->maxdeg = (int32_t)std::min<int64_t>(maxdeg, INT32_MAX);
+    L.n = n;
+    L.nnz = nnz;
+    L.directed = directed;
+    L.wmax = wmax;
+    L.maxdeg = (int32_t)std::min<int64_t>(maxdeg, INT32_MAX);
     const int colbits = bit_width_u64((uint64_t)(n - 1));
     const int wbits = bit_width_u64((uint64_t)(wmax - 1));
-    g->packed = colbits + wbits <= 32 && wbits < 32;
-    g->wshift = g->packed ? (uint32_t)wbits : 0u;
-    g->wmask = g->packed ? (wbits == 0 ? 0u : (uint32_t)((1ull << wbits) - 1)) : 0u;
-    g->wbytes = wmax <= 255 ? 1 : (wmax <= 65535 ? 2 : 4);
+    L.packed = colbits + wbits <= 32 && wbits < 32;
+    L.wshift = L.packed ? (uint32_t)wbits : 0u;
+    L.wmask = L.packed ? (wbits == 0 ? 0u : (uint32_t)((1ull << wbits) - 1)) : 0u;
+    L.wbytes = wmax <= 255 ? 1 : (wmax <= 65535 ? 2 : 4);
     int64_t nz_rows = 0;
     for (int32_t v = 0; v < n; ++v)
         nz_rows += row_ptr[v + 1] > row_ptr[v];
-    g->avg_deg = nz_rows ? (double)nnz / (double)nz_rows : 0.0;
+    L.avg_deg = nz_rows ? (double)nnz / (double)nz_rows : 0.0;
     double wsum = 0;
     for (int64_t e = 0; e < nnz; ++e)
         wsum += w[e];
-    g->wmean = nnz ? wsum / (double)nnz : 1.0;
+    L.wmean = nnz ? wsum / (double)nnz : 1.0;
 
     // Renumber skewed graphs by decreasing in-degree (ties keep the caller's
     // order): the most frequent arc heads get the lowest ids, whose distances
@@ -325,10 +325,11 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
     const int64_t *irow = row_ptr;
     const int32_t *icol = col, *iw = w;
     if (!order.empty()) {
-        g->renumbered = true;
-        g->host_iperm.assign((size_t)n, 0);
+        L.renumbered = true;
+        L.perm = order;
+        L.iperm.assign((size_t)n, 0);
         for (int32_t v = 0; v < n; ++v)
-            g->host_iperm[(size_t)order[(size_t)v]] = v;
+            L.iperm[(size_t)order[(size_t)v]] = v;
         rrow.assign((size_t)n + 1, 0);
         rcol.resize((size_t)nnz);
         rw.resize((size_t)nnz);
@@ -338,7 +339,7 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
             const int32_t o = order[(size_t)v];
             int64_t at = rrow[(size_t)v];
             for (int64_t e = row_ptr[o]; e < row_ptr[o + 1]; ++e, ++at) {
-                rcol[(size_t)at] = g->host_iperm[(size_t)col[e]];
+                rcol[(size_t)at] = L.iperm[(size_t)col[e]];
                 rw[(size_t)at] = w[e];
                 if (want_edges)
                     ce[(size_t)at] = (uint32_t)e;
@@ -348,39 +349,27 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
         irow = rrow.data();
         icol = rcol.data();
         iw = rw.data();
-        g->perm.alloc((size_t)n * 4);
-        g->iperm.alloc((size_t)n * 4);
-        hip_check(hipMemcpy(g->perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice),
-                  "upload numbering");
-        hip_check(hipMemcpy(g->iperm.p, g->host_iperm.data(), (size_t)n * 4,
-                            hipMemcpyHostToDevice),
-                  "upload numbering");
     }
-    upload_arcs(g.get(), n, irow, icol, iw, g->row, g->arc, g->wt);
+    pack_csr(L, n, irow, icol, iw, L.row, L.arc, L.wt);
     std::vector<uint32_t> tsrc;
     if (directed) {
         if (!order.empty() || want_edges)
             build_transpose(n, irow, icol, iw, trow, tcol, tw, want_edges ? &tsrc : nullptr);
-        upload_arcs(g.get(), n, trow.data(), tcol.data(), tw.data(), g->trow, g->tarc, g->twt);
+        pack_csr(L, n, trow.data(), tcol.data(), tw.data(), L.trow, L.tarc, L.twt);
     }
+    L.edges = want_edges;
     if (want_edges && nnz > 0) {
         // The dependency pass records a DAG arc u -> w at a position p of w's
         // in-row; emap[p] is the caller's index of that arc.
-        std::vector<uint32_t> emap((size_t)nnz);
+        L.emap.resize((size_t)nnz);
         std::vector<uint32_t> rev;
         if (!directed)
             rev = reverse_arcs(n, irow, icol, iw);
         for (int64_t p = 0; p < nnz; ++p) {
             const uint32_t dev_arc = directed ? tsrc[(size_t)p] : rev[(size_t)p];
-            emap[(size_t)p] = ce.empty() ? dev_arc : ce[dev_arc];
+            L.emap[(size_t)p] = ce.empty() ? dev_arc : ce[dev_arc];
         }
-        g->emap.alloc((size_t)nnz * 4);
-        hip_check(hipMemcpy(g->emap.p, emap.data(), (size_t)nnz * 4, hipMemcpyHostToDevice),
-                  "upload arc map");
     }
-    g->edges_ready = want_edges;
-    hip_check(hipStreamSynchronize(g->stream), "graph upload");
-    *out = g.release();
 }
 
 // Argument checks shared by both ingest paths (host and device arrays).
@@ -416,6 +405,51 @@ static void init_graph_runtime(bc_graph *g)
     g->plain_ctl.alloc(sizeof(PlainCtl));
     hip_check(hipHostMalloc((void **)&g->host_counters, sizeof(DevCounters)), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&g->host_plain, sizeof(PlainCtl)), "hipHostMalloc");
+}
+
+template <class T> static void upload(DevBuf &d, const std::vector<T> &h, const char *what)
+{
+    if (h.empty())
+        return;
+    d.alloc(h.size() * sizeof(T));
+    hip_check(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), what);
+}
+
+static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *w, uint32_t flags, bc_graph **out)
+{
+    check_create_args(n, nnz, row_ptr, col, w, flags, out);
+    HostLayout L;
+    build_host_layout(n, nnz, row_ptr, col, w, flags, L);
+
+    ensure_device();
+    std::unique_ptr<bc_graph> g(new bc_graph());
+    init_graph_runtime(g.get());
+    g->n = L.n;
+    g->nnz = L.nnz;
+    g->directed = L.directed;
+    g->wmax = L.wmax;
+    g->maxdeg = L.maxdeg;
+    g->packed = L.packed;
+    g->wshift = L.wshift;
+    g->wmask = L.wmask;
+    g->wbytes = L.wbytes;
+    g->avg_deg = L.avg_deg;
+    g->wmean = L.wmean;
+    g->renumbered = L.renumbered;
+    g->host_iperm = L.iperm;
+    upload(g->perm, L.perm, "upload numbering");
+    upload(g->iperm, L.iperm, "upload numbering");
+    upload(g->row, L.row, "upload row offsets");
+    upload(g->arc, L.arc, "upload arcs");
+    upload(g->wt, L.wt, "upload weights");
+    upload(g->trow, L.trow, "upload in-row offsets");
+    upload(g->tarc, L.tarc, "upload in-arcs");
+    upload(g->twt, L.twt, "upload in-arc weights");
+    upload(g->emap, L.emap, "upload arc map");
+    g->edges_ready = L.edges;
+    hip_check(hipStreamSynchronize(g->stream), "graph upload");
+    *out = g.release();
 }
 
 DevGraph bc_graph::view() const
@@ -568,6 +602,20 @@ void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, 
     per_cu = std::max(per_cu, 1);
 }
 
+int64_t batch_cap(bc_graph *g)
+{
+    // keep the slabs within half of the free device memory (the graph's own
+    // slabs count as free: a larger set replaces them)
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const size_t stride = slab_layout(g->n, g->nnz).stride;
+    const size_t have = g->batched.base.p ? (size_t)g->batched.nslabs * stride : 0;
+    const int64_t by_mem = (int64_t)((free_b + have) / 2 / std::max<size_t>(stride, 1));
+    if (by_mem < 1)
+        throw bc_error(BC_E_NOMEM, "one state slab (%zu bytes) does not fit", stride);
+    return std::min<int64_t>(by_mem, 65535);
+}
+
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
 {
     ResolvedOptions r;
@@ -620,16 +668,7 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     const int fill = g->num_cus * per_cu;
     int64_t b = o.batch ? o.batch : fill;
     b = std::min<int64_t>(b, std::max<int64_t>(k, 1));
-    // keep the slabs within half of the free device memory
-    size_t free_b = 0, total_b = 0;
-    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-    const size_t stride = slab_layout(g->n, g->nnz).stride;
-    const size_t have = g->batched.base.p ? (size_t)g->batched.nslabs * stride : 0;
-    const int64_t by_mem = (int64_t)((free_b + have) / 2 / std::max<size_t>(stride, 1));
-    if (by_mem < 1)
-        throw bc_error(BC_E_NOMEM, "one state slab (%zu bytes) does not fit", stride);
-    b = std::min<int64_t>(b, by_mem);
-    b = std::min<int64_t>(b, 65535);
+    b = std::min<int64_t>(b, batch_cap(g));
     r.batch = (int)std::max<int64_t>(b, 1);
     r.autotune = o.autotune;
     return r;
@@ -966,7 +1005,12 @@ bc_status bc_create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr_
 
 bc_status bc_destroy_graph(bc_graph *g)
 {
-    return guarded([&] { delete g; });
+    return guarded([&] {
+        if (g && g->server_refs.load() > 0)
+            throw bc_error(BC_E_BUSY, "the graph is held by %d live server(s); destroy them first",
+                           g->server_refs.load());
+        delete g;
+    });
 }
 
 bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info)
@@ -985,6 +1029,16 @@ bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info)
         i.renumbered = g->renumbered;
         i.device_bytes = (int64_t)(g->row.bytes + g->arc.bytes + g->wt.bytes + g->trow.bytes +
                                    g->tarc.bytes + g->twt.bytes);
+        i.tuned = g->tuned.valid;
+        i.tuned_delta = g->tuned.delta;
+        i.tuned_wg_threads = g->tuned.wg_threads;
+        i.tuned_lane_max_deg = g->tuned.lane_max;
+        i.tuned_dep_mode = g->tuned.dep_mode;
+        i.tuned_expand_lane_deg = g->tuned.lane_deg;
+        i.tuned_wave_max_deg = g->tuned.wave_deg;
+        i.tuned_wg_min_deg = g->tuned.wg_deg;
+        i.tuned_batch = g->tuned.batch;
+        i.tuning_trials = g->tune_trials;
         *info = i;
     });
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/bc.h"
@@ -67,7 +68,7 @@ struct TunedOptions {
     bool valid = false;
     int delta = 0, lane_max = 0, wg_threads = 0, dep_mode = 0;
     int lane_deg = 0, wave_deg = 0, wg_deg = 0;
-    int batch = 0; // sources in flight chosen for the tuning call's source count
+    int batch = 0; // sources in flight (0 = the full occupancy of wg_threads)
     double best_ms_per_source = 0.0;
 };
 
@@ -110,6 +111,8 @@ struct bc_graph {
 
     Workspace batched, plain;
     TunedOptions tuned;
+    int64_t tune_trials = 0; // timed autotuner candidates so far
+    std::atomic<int> server_refs{0}; // live servers that hold this graph
     bool last_stats_valid = false;
     bc_stats last_stats{};
 
@@ -134,6 +137,9 @@ int lds_bits_for(const bc_graph *g, int requested);
 void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
                       int &H, int &per_cu);
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
+// Most state slabs a batched launch may use (half of the free device memory,
+// at most 65535).
+int64_t batch_cap(bc_graph *g);
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
                     const bc_options *opt, double *bc_dev, bc_stats *stats,
                     double *ebc_dev = nullptr);

@@ -18,6 +18,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -74,6 +75,8 @@ struct GraphEntry {
     bc_graph *g = nullptr;
     int64_t m = 0; // edges for throughput accounting
     std::vector<std::unique_ptr<SweepCtx>> ctx;
+    int fail_status = 0; // its sweep contexts could not be created: fail the sweep
+    std::string fail_msg;
 };
 
 class HipExec {
@@ -89,6 +92,7 @@ class HipExec {
         e.g = g;
         e.m = g->directed ? g->nnz : g->nnz / 2;
         graphs_.push_back(std::move(e));
+        g->server_refs.fetch_add(1); // bc_destroy_graph refuses it until the server ends
         index_[g] = (int)graphs_.size() - 1;
         return (int)graphs_.size() - 1;
     }
@@ -99,7 +103,9 @@ class HipExec {
     {
         GraphEntry &e = graphs_[(size_t)gidx];
         if (e.ctx.empty())
-            create_contexts(e, gidx);
+            try_create_contexts(e, gidx);
+        if (e.fail_status)
+            return 1; // one sweep that fails its items (see launch)
         int f = 0;
         for (auto &c : e.ctx)
             f += !c->busy;
@@ -136,6 +142,17 @@ class HipExec {
     void launch(int gidx, const std::vector<bcserve::SweepItem> &items)
     {
         GraphEntry &e = graphs_[(size_t)gidx];
+        if (e.fail_status) {
+            // no context for this graph: its items fail, other graphs go on;
+            // the next request of the graph tries to create the contexts again
+            bcserve::Finished f;
+            f.graph = gidx;
+            f.items = items;
+            f.err_status = e.fail_status;
+            failed_.push_back(std::move(f));
+            e.fail_status = 0;
+            return;
+        }
         SweepCtx *c = nullptr;
         for (auto &x : e.ctx)
             if (!x->busy) {
@@ -201,6 +218,9 @@ class HipExec {
 
     void poll(std::vector<bcserve::Finished> &fin)
     {
+        for (auto &f : failed_)
+            fin.push_back(std::move(f));
+        failed_.clear();
         for (size_t gi = 0; gi < graphs_.size(); ++gi)
             for (auto &c : graphs_[gi].ctx) {
                 if (!c->busy)
@@ -232,7 +252,9 @@ class HipExec {
     {
         GraphEntry &e = graphs_[(size_t)gidx];
         if (e.ctx.empty())
-            create_contexts(e, gidx);
+            try_create_contexts(e, gidx);
+        if (e.fail_status)
+            return 1 << 30; // every pending item of the graph goes into the failing sweep
         return e.ctx.front()->cap;
     }
 
@@ -247,6 +269,8 @@ class HipExec {
     ~HipExec()
     {
         drain();
+        for (auto &e : graphs_)
+            e.g->server_refs.fetch_sub(1);
         graphs_.clear();
         if (admin_)
             (void)hipStreamDestroy(admin_);
@@ -299,6 +323,22 @@ class HipExec {
         return g->tuned.valid ? g->tuned.wg_threads : 256;
     }
 
+    // Creates the graph's sweep contexts; on failure (not enough device
+    // memory, a failed allocation) leaves none and records the status, so
+    // that only this graph's requests fail.
+    void try_create_contexts(GraphEntry &e, int gidx)
+    {
+        e.fail_status = 0;
+        try {
+            create_contexts(e, gidx);
+        } catch (const bc_error &err) {
+            e.ctx.clear();
+            (void)hipGetLastError();
+            e.fail_status = err.status;
+            e.fail_msg = err.msg;
+        }
+    }
+
     void create_contexts(GraphEntry &e, int gidx)
     {
         bc_graph *g = e.g;
@@ -313,8 +353,20 @@ class HipExec {
         int slots = opts_.slots_per_sweep ? opts_.slots_per_sweep : std::max(32, fill / 4);
         const int64_t by_mem = (int64_t)(opts_.slab_bytes_per_sweep / std::max<size_t>(L.stride, 1));
         slots = (int)std::max<int64_t>(1, std::min<int64_t>(slots, by_mem));
-        const int cap = opts_.items_per_sweep ? opts_.items_per_sweep : std::max(64, 2 * slots);
         const int nctx = opts_.sweeps_per_graph ? opts_.sweeps_per_graph : 2;
+        // at most half of the memory free now goes to this graph's contexts,
+        // beyond the reserve, so that other graphs and results still fit
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        const size_t avail = free_b > reserve_ ? (free_b - reserve_) / 2 : 0;
+        const int64_t fit = (int64_t)(avail / ((size_t)nctx * std::max<size_t>(L.stride, 1)));
+        if (fit < 1)
+            throw bc_error(BC_E_NOMEM,
+                           "sweep contexts of a graph with n = %d need %zu bytes per source; "
+                           "%zu bytes are free",
+                           g->n, L.stride, free_b);
+        slots = (int)std::min<int64_t>(slots, fit);
+        const int cap = opts_.items_per_sweep ? opts_.items_per_sweep : std::max(64, 2 * slots);
         for (int i = 0; i < nctx; ++i) {
             auto c = std::make_unique<SweepCtx>();
             c->gidx = gidx;
@@ -347,6 +399,7 @@ class HipExec {
     std::vector<GraphEntry> graphs_;
     std::map<bc_graph *, int> index_;
     std::map<uint64_t, double *> *outs_ = nullptr;
+    std::vector<bcserve::Finished> failed_; // sweeps failed without a launch
     hipStream_t admin_ = nullptr;
     int64_t sweeps_ = 0;
 };

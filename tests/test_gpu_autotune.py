@@ -1,0 +1,75 @@
+"""The autotuner (bc_options.autotune) on the GPU, through the C ABI: a tuned
+computation matches the oracle, the choice is cached on the graph and reused
+by later calls without timing candidates again, and fields the caller sets
+are kept."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_05975_amd import bc, graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+SETTINGS = ["delta", "wg_threads", "lane_max_deg", "dep_mode", "expand_lane_deg",
+            "wave_max_deg", "wg_min_deg"]
+
+
+def rel_close(got, want, tol):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    zero = want == 0
+    assert np.all(got[zero] == 0), np.nonzero(got[zero])[0][:10]
+    nz = ~zero
+    err = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
+    assert err.size == 0 or err.max() <= tol, (float(err.max()), int(np.argmax(err)))
+
+
+def hub_graph():
+    """Directed graph with two hubs of 1500 and 900 out-arcs over a sparse
+    random part, tie-heavy weights: every expansion tier has vertices."""
+    rng = np.random.default_rng(43)
+    n = 2500
+    src = [0] * 1500 + [1] * 900
+    dst = list(range(2, 1502)) + list(range(1600, 2500))
+    a = rng.integers(0, n, size=6000)
+    b = rng.integers(0, n, size=6000)
+    keep = a != b
+    src += a[keep].tolist()
+    dst += b[keep].tolist()
+    w = rng.integers(1, 4, size=len(src))
+    return gg.csr_from_arcs(n, src, dst, w, directed=True)
+
+
+@pytest.mark.parametrize("which", ["ba", "hubs"])
+def test_autotune_parity_and_cached_choice(which):
+    g = gg.ba_graph(5000, 4, 1, 300, seed=41) if which == "ba" else hub_graph()
+    srcs = gg.sample_sources(g, 1500, seed=42)
+    G = bc.Graph(g)
+    assert G.info()["tuned"] == 0 and G.info()["tuning_trials"] == 0
+    got, st = G.bc(srcs, autotune=1)
+    rel_close(got, oracle.oracle_bc(g, srcs), 1e-9)
+    info = G.info()
+    assert info["tuned"] == 1 and info["tuning_trials"] >= 15, info
+    for name in SETTINGS:
+        assert st[name] == info["tuned_" + name], (name, st[name], info)
+    if info["tuned_batch"]:
+        assert st["batch"] == min(info["tuned_batch"], len(srcs))
+    trials = info["tuning_trials"]
+    # a later call reuses the cached choice: no candidate is timed again
+    sub = srcs[:400]
+    got2, st2 = G.bc(sub, autotune=1)
+    assert G.info()["tuning_trials"] == trials
+    for name in SETTINGS:
+        assert st2[name] == st[name], name
+    rel_close(got2, oracle.oracle_bc(g, sub), 1e-9)
+    # settings the caller fixes are kept, the rest is tuned around them
+    H = bc.Graph(g)
+    got3, st3 = H.bc(srcs, autotune=1, delta=7, wg_threads=512, wave_max_deg=32)
+    assert st3["delta"] == 7 and st3["wg_threads"] == 512 and st3["wave_max_deg"] == 32
+    hi = H.info()
+    assert hi["tuned_delta"] == 7 and hi["tuned_wg_threads"] == 512
+    rel_close(got3, oracle.oracle_bc(g, srcs), 1e-9)
+    G.close()
+    H.close()
