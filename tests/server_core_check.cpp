@@ -32,13 +32,14 @@ struct FakeExec {
     }
     void poll(std::vector<Finished> &out) { for (auto &f : ready) out.push_back(f); ready.clear(); }
     // finish the oldest running sweep; optionally mark one item (index) failed
-    void finish_oldest(int fail_index = -1) {
+    void finish_oldest(int fail_index = -1, int err_status = 0) {
         auto s = running.front();
         running.erase(running.begin());
         busy[s.first] -= 1;
         Finished f;
         f.graph = s.first;
         f.items = s.second;
+        f.err_status = err_status;
         f.item_status = 5;
         f.item_fail.assign(f.items.size(), 0);
         if (fail_index >= 0) f.item_fail[(size_t)fail_index] = 1;
@@ -156,7 +157,27 @@ int main() {
         sc.step(2.0);
         CHECK(sc.find(b)->phase == ReqPhase::Active);
     }
-    // 6. percentile (nearest rank)
+    // 6. a sweep that fails as a whole (the executor found no memory for the
+    //    graph's state): the requests of that graph fail with its status, the
+    //    other graph's request completes
+    {
+        FakeExec ex; ex.cap = 8;
+        Policy p; p.budget_bytes = 1 << 20;
+        Scheduler<FakeExec> sc(ex, p);
+        uint64_t a = sc.submit(0, s3.data(), 3, 8, 0.0);
+        uint64_t b = sc.submit(1, s10.data(), 10, 8, 0.0);
+        sc.step(0.1);
+        CHECK(ex.running.size() == 3); // graph 0: one sweep; graph 1: 8 + 2 items
+        while (!ex.running.empty()) {
+            const int g = ex.running.front().first;
+            ex.finish_oldest(-1, g == 1 ? 6 : 0);
+            sc.step(0.2);
+        }
+        CHECK(sc.find(a)->phase == ReqPhase::Done && sc.find(a)->status == 0);
+        CHECK(sc.find(b)->phase == ReqPhase::Failed && sc.find(b)->status == 6);
+        CHECK(sc.idle());
+    }
+    // 7. percentile (nearest rank)
     {
         std::vector<double> v = {5, 1, 4, 2, 3};
         CHECK(percentile(v, 50) == 3 && percentile(v, 99) == 5 && percentile({}, 50) == 0);
