@@ -47,20 +47,6 @@ WORKLOADS = {
 }
 
 
-def serving_graphs():
-    from paper_1701_05975_amd import graphgen as gg
-    return [
-        gg.er_graph(10_000, 40_000, 1, 100, seed=101),
-        gg.er_graph(500_000, 2_000_000, 1, 100, seed=102),
-        gg.ba_graph(50_000, 5, 1, 1000, seed=103),
-        gg.ba_graph(1_000_000, 5, 1, 1000, seed=104),
-        gg.grid_graph(100, 100, 396, 1, 255, seed=105),
-        gg.grid_graph(1414, 1414, 79_941, 1, 255, seed=106),
-        gg.rmat_graph(14, 16 << 14, .57, .19, .19, 1, 255, seed=107),
-        gg.rmat_graph(21, 16 << 21, .57, .19, .19, 1, 255, seed=108),
-    ]
-
-
 ABLATION_VARIANTS = [
     # (name, options) -- the paper's four thread mappings (Sec. 3.3-3.4, Figs. 3-5)
     # recast for 64-lane waves, plus the adaptive default of this library
@@ -192,42 +178,53 @@ def run_dynamic(args):
 
 
 def run_serving(args):
-    """Open-loop serving run: Poisson arrivals at a fixed rate, latency from
-    arrival to completion measured inside the server."""
+    """Open-loop serving run: Poisson arrivals at the fixed rate stored with
+    the launch settings (or calibrated with --calibrate), latency from arrival
+    to completion measured inside the server; the first requests of the stream
+    are warm-up and left out of the percentiles."""
     # sweeps of different graphs run on their own streams; give them hardware
     # queues of their own (HIP reads this before the runtime starts)
     os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
     import torch  # noqa: F401  (one HIP runtime for the process)
     from paper_1701_05975_amd import bc, graphgen as gg
+    from paper_1701_05975_amd.launch import SERVING
 
+    nreq = args.requests or SERVING["requests"]
+    warm = args.serve_warmup if args.serve_warmup >= 0 else SERVING["warmup"]
+    if not 0 <= warm < nreq:
+        raise SystemExit("serving: need 0 <= warm-up < requests")
     t0 = time.perf_counter()
-    graphs = serving_graphs()
+    graphs = gg.serving_graphs()
     print(f"# generated 8 graphs in {time.perf_counter() - t0:.1f}s: " +
           ", ".join(f"{g.name}(n={g.n},m={g.m})" for g in graphs), file=sys.stderr, flush=True)
     G = [bc.Graph(g) for g in graphs]
     print("# graphs resident on the device", file=sys.stderr, flush=True)
-    rng = np.random.default_rng(200)
-    nreq = args.requests
-    reqs = []
-    for i in range(nreq):
-        gi = int(rng.integers(0, len(graphs)))
-        k = int(np.floor(np.exp(rng.uniform(np.log(64), np.log(4096)))))
-        reqs.append((gi, gg.sample_sources(graphs[gi], k, seed=10_000 + i)))
+    reqs = gg.serving_requests(graphs, nreq)
     work = np.array([len(s) * graphs[gi].m for gi, s in reqs], dtype=np.float64)
-    sv = bc.Server(order=args.order)
-    # capacity estimate: the warm-up requests served back to back (closed loop)
-    warm = args.serve_warmup
-    tw = time.perf_counter()
-    ts = [sv.submit(G[gi], s) for gi, s in reqs[:warm]]
-    for (gi, s), t in zip(reqs[:warm], ts):
-        _, ms = sv.wait(t, graphs[gi].n)
-        print(f"# warm-up request: graph {graphs[gi].name} k={len(s)} {ms:.1f} ms",
-              file=sys.stderr, flush=True)
-    cap = work[:warm].sum() / (time.perf_counter() - tw)  # edges*sources per second
-    lam = args.rate if args.rate > 0 else args.load * cap / work.mean()
-    print(f"# warm-up: {warm} requests, capacity ~{cap / 1e9:.2f} GTEPS; "
-          f"arrival rate {lam:.3f} req/s", file=sys.stderr, flush=True)
-    sv.close()
+    if args.calibrate:
+        # capacity: a prefix of the stream submitted at once and served closed loop
+        ncal = min(nreq, 64)
+        sv = bc.Server(order=args.order)
+        tw = time.perf_counter()
+        ts = [sv.submit(G[gi], s) for gi, s in reqs[:ncal]]
+        for (gi, s), t in zip(reqs[:ncal], ts):
+            sv.wait(t, graphs[gi].n)
+        cap = work[:ncal].sum() / (time.perf_counter() - tw)  # sources x edges per second
+        sv.close()
+        lam = args.load * cap / work.mean()
+        print(json.dumps({"calibration": {"capacity_gteps": round(cap / 1e9, 4),
+                                          "load": args.load, "mean_work": float(work.mean()),
+                                          "rate_req_per_s": round(lam, 4),
+                                          "requests": ncal}}), flush=True)
+        return
+    lam = args.rate if args.rate > 0 else SERVING["rate"]
+    if lam <= 0:
+        raise SystemExit("serving: no arrival rate stored; run with --calibrate first")
+    print(f"# arrival rate {lam:.4f} req/s, {nreq} requests ({warm} warm-up)",
+          file=sys.stderr, flush=True)
+    # results kept for the mix-vs-alone check: requests spread over the measured part
+    keep = set(np.linspace(warm, nreq - 1, min(args.serve_checks, nreq - warm))
+               .round().astype(int).tolist())
     sv = bc.Server(order=args.order)
     gaps = np.random.default_rng(201).exponential(1.0 / lam, size=nreq)
     start = time.perf_counter()
@@ -245,40 +242,51 @@ def run_serving(args):
         lat.append(ms)
         print(f"# request {i}: graph {graphs[gi].name} k={len(s)} latency {ms:.1f} ms",
               file=sys.stderr, flush=True)
-        if i in (1, nreq // 2, nreq - 1):
+        if i in keep:
             results[i] = out
+    wall = time.perf_counter() - start
     st = sv.stats()
     sv.close()
-    # each spot-checked result must equal the same request computed alone
+    # each kept result must equal the same request computed alone
     worst = 0.0
-    for i, out in results.items():
+    for i, out in sorted(results.items()):
         gi, s = reqs[i]
         alone, _ = G[gi].bc(s)
         nz = alone != 0
-        assert np.all(out[~nz] == 0)
+        assert np.all(out[~nz] == 0), i
         if nz.any():
             worst = max(worst, float(np.max(np.abs(out[nz] - alone[nz]) / np.abs(alone[nz]))))
     assert worst <= 1e-9, worst
-    lat = np.array(lat)
+    print(f"# mix vs alone on {len(results)} requests: max rel err {worst:.2e}",
+          file=sys.stderr, flush=True)
+    meas = np.array(lat[warm:])
     rec = {
         "metric": "served BC request latency p50/p99 at a fixed Poisson rate; aggregate GTEPS",
-        "value": round(float(np.percentile(lat, 50)), 2),
+        "value": round(float(np.percentile(meas, 50)), 2),
         "unit": "ms (p50)",
-        "p50_ms": round(float(np.percentile(lat, 50)), 2),
-        "p99_ms": round(float(np.percentile(lat, 99)), 2),
-        "mean_ms": round(float(lat.mean()), 2),
+        "p50_ms": round(float(np.percentile(meas, 50)), 2),
+        "p99_ms": round(float(np.percentile(meas, 99)), 2),
+        "mean_ms": round(float(meas.mean()), 2),
+        "max_ms": round(float(meas.max()), 2),
         "gteps": round(st["gteps"], 4),
+        "offered_gteps": round(float(lam * work.mean() / 1e9), 4),
         "n_gpus": 1,
         "requests": nreq,
+        "warmup_requests": warm,
+        "measured_requests": int(meas.size),
         "rate_req_per_s": round(lam, 4),
+        "wall_s": round(wall, 2),
         "higher_is_better": False,
         "sweeps": st["sweeps"],
+        "mix_vs_alone_checked": len(results),
         "mix_vs_alone_max_rel_err": worst,
         "data": "synthetic (seeded generators)",
-        "config": {"workload": f"serving: {WORKLOADS['serving']}", "load": args.load, "order": "fewest left first" if args.order == 1 else "oldest first",
+        "config": {"workload": f"serving: {WORKLOADS['serving']}",
+                   "order": "fewest left first" if args.order == 1 else "oldest first",
                    "graphs": [f"{g.name} n={g.n} m={g.m}" for g in graphs]},
     }
     print(json.dumps(rec), flush=True)
+
 
 HBM_PEAK_GBS = 8000.0
 
@@ -389,12 +397,19 @@ def main():
                     help="sources timed in the source-interleaved form (0: skip)")
     ap.add_argument("--ablation-sources", type=int, default=256)
     ap.add_argument("--variants", default="", help="ablation: comma-separated name parts to run")
-    ap.add_argument("--requests", type=int, default=24, help="serving: requests in the run")
+    ap.add_argument("--requests", type=int, default=0,
+                    help="serving: requests in the run (0 = the stored setting, 512)")
     ap.add_argument("--order", type=int, default=1,
                     help="serving: 1 = fewest sources left first within a graph, 0 = oldest first")
-    ap.add_argument("--serve-warmup", type=int, default=4, help="serving: warm-up requests")
-    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load vs capacity")
-    ap.add_argument("--rate", type=float, default=0.0, help="serving: fixed arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=-1,
+                    help="serving: warm-up requests left out of the percentiles (-1 = stored, 32)")
+    ap.add_argument("--serve-checks", type=int, default=32,
+                    help="serving: measured requests whose result is compared with a lone run")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="serving: measure capacity and print the arrival rate for a load")
+    ap.add_argument("--load", type=float, default=0.7, help="serving --calibrate: offered load")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving: arrival rate (0 = the stored rate)")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -387,3 +387,37 @@ def config_sources(name: str, g: CSRGraph, parity: bool = False) -> np.ndarray:
     if k is None:
         return np.arange(g.n, dtype=np.int32)
     return sample_sources(g, k, cfg["src_seed"])
+
+
+# The serving workload: eight resident graphs of the four families, n from 10k
+# to 2M, and a seeded request stream over them.
+SERVING_GRAPHS = [
+    lambda: er_graph(10_000, 40_000, 1, 100, seed=101),
+    lambda: er_graph(500_000, 2_000_000, 1, 100, seed=102),
+    lambda: ba_graph(50_000, 5, 1, 1000, seed=103),
+    lambda: ba_graph(1_000_000, 5, 1, 1000, seed=104),
+    lambda: grid_graph(100, 100, 396, 1, 255, seed=105),
+    lambda: grid_graph(1414, 1414, 79_941, 1, 255, seed=106),
+    lambda: rmat_graph(14, 16 << 14, .57, .19, .19, 1, 255, seed=107),
+    lambda: rmat_graph(21, 16 << 21, .57, .19, .19, 1, 255, seed=108),
+]
+
+
+def serving_graphs(which=None) -> list:
+    """The serving graphs (all eight, or those whose indices are listed)."""
+    idx = range(len(SERVING_GRAPHS)) if which is None else which
+    return [SERVING_GRAPHS[i]() for i in idx]
+
+
+def serving_requests(graphs: list, nreq: int) -> list:
+    """The seeded request stream over the serving graphs: (graph index, source
+    list) per request, the graph uniform over the eight and k log-uniform in
+    [64, 4096].  Sources depend only on the request index and its graph."""
+    rng = np.random.default_rng(200)
+    reqs = []
+    for i in range(nreq):
+        gi = int(rng.integers(0, len(SERVING_GRAPHS)))
+        k = int(np.floor(np.exp(rng.uniform(np.log(64), np.log(4096)))))
+        g = graphs[gi]
+        reqs.append((gi, sample_sources(g, k, seed=10_000 + i) if g is not None else None))
+    return reqs

@@ -12,3 +12,9 @@ LAUNCH = {
     "grid1000": dict(delta=182, wg_threads=1024, lane_max_deg=128, batch=256),
     "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
 }
+
+# Serving run over the eight resident graphs: the Poisson arrival rate is
+# fixed (measured once with `python bench.py --config serving --calibrate` at
+# 0.7 of the closed-loop capacity of the stream's first 64 requests), and the
+# first `warmup` requests of the `requests` are left out of the percentiles.
+SERVING = dict(rate=0.0, requests=512, warmup=32)

@@ -53,6 +53,41 @@ def test_mix_equals_alone_and_oracle():
     sv.close()
 
 
+def test_serving_stream_requests_on_small_graphs():
+    """32 requests of the benchmark's serving stream (those that fall on its
+    graphs of at most 50k vertices) served together in a mix: each result
+    equals the same request computed alone and the oracle, within 1e-9."""
+    small = [i for i, b in enumerate(gg.SERVING_GRAPHS) if i in (0, 2, 4, 6)]
+    graphs = [None] * len(gg.SERVING_GRAPHS)
+    for i, g in zip(small, gg.serving_graphs(small)):
+        assert g.n <= 50_000
+        graphs[i] = g
+    reqs = [(i, r) for i, r in enumerate(gg.serving_requests(graphs, 200)) if r[1] is not None][:32]
+    assert len(reqs) == 32
+    G = {i: bc.Graph(graphs[i]) for i in small}
+    sv = bc.Server()
+    tickets = []
+    for j, (_, (gi, src)) in enumerate(reqs):
+        tickets.append(sv.submit(G[gi], src))
+        if j % 4 == 3:
+            time.sleep(0.005)  # later requests arrive while earlier ones run
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        want = [ex.submit(oracle.oracle_bc, graphs[gi], src, oracle.host_threads())
+                for _, (gi, src) in reqs]
+        for (i, (gi, src)), t, w in zip(reqs, tickets, want):
+            got, lat = sv.wait(t, graphs[gi].n)
+            alone, _ = G[gi].bc(src)
+            rel_close(got, alone, 1e-9)
+            rel_close(got, w.result(), 1e-9)
+            assert lat > 0, i
+    st = sv.stats()
+    assert st["completed"] == 32 and st["failed"] == 0
+    sv.close()
+    for g in G.values():
+        g.close()
+
+
 def test_failure_isolated_to_its_request():
     bad = bc.Graph(gg.diamond_chain(64))
     good_g = gg.path_graph(50)
