@@ -227,23 +227,42 @@ def run_serving(args):
                .round().astype(int).tolist())
     sv = bc.Server(order=args.order)
     gaps = np.random.default_rng(201).exponential(1.0 / lam, size=nreq)
+    # completions are collected (in submission order) by a second thread while
+    # arrivals continue, so that finished results are released as they come
+    import queue
+    import threading
+    pending = queue.Queue()
+    lat = [0.0] * nreq
+    results = {}
+    failure = []
+
+    def collect():
+        try:
+            for _ in range(nreq):
+                i, gi, s, t = pending.get()
+                out, ms = sv.wait(t, graphs[gi].n)
+                lat[i] = ms
+                print(f"# request {i}: graph {graphs[gi].name} k={len(s)} latency {ms:.1f} ms",
+                      file=sys.stderr, flush=True)
+                if i in keep:
+                    results[i] = out
+        except BaseException as e:  # reported by the main thread
+            failure.append(e)
+
+    waiter = threading.Thread(target=collect, daemon=True)
+    waiter.start()
     start = time.perf_counter()
     arrivals = start + np.cumsum(gaps)
-    tickets = []
-    for (gi, s), ta in zip(reqs, arrivals):
+    for i, ((gi, s), ta) in enumerate(zip(reqs, arrivals)):
         dt = ta - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        tickets.append(sv.submit(G[gi], s))
-    lat = []
-    results = {}
-    for i, ((gi, s), t) in enumerate(zip(reqs, tickets)):
-        out, ms = sv.wait(t, graphs[gi].n)
-        lat.append(ms)
-        print(f"# request {i}: graph {graphs[gi].name} k={len(s)} latency {ms:.1f} ms",
-              file=sys.stderr, flush=True)
-        if i in keep:
-            results[i] = out
+        pending.put((i, gi, s, sv.submit(G[gi], s)))
+        if failure:
+            break
+    waiter.join()
+    if failure:
+        raise failure[0]
     wall = time.perf_counter() - start
     st = sv.stats()
     sv.close()
