@@ -257,6 +257,28 @@ bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
                             const bc_options *opt, double *bc_dev, bc_stats *stats);
 
 /*
+ * bc_compute_device_noalloc -- as bc_compute_device in the batched form, for
+ * callers that cannot allocate device memory during the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
+ * calls no hipMalloc, hipFree or other allocating routine: the per-source
+ * state slabs live in a fixed device array of BC_NOALLOC_SCRATCH_BYTES that
+ * each GPU holds from the library's load until the process ends.  The
+ * caller still provides sources_dev[k] and bc_dev[n] (device memory).
+ *
+ * Sources in flight are capped by how many state slabs fit in the array; a
+ * graph whose single slab (about 76 bytes per vertex plus 4 per arc) does not
+ * fit gives BC_E_NOMEM and leaves bc_dev untouched.  Only the batched form
+ * runs here: opt->mode other than BC_MODE_AUTO / BC_MODE_BATCHED, or
+ * opt->autotune set, gives BC_E_INVAL.  Every call on one GPU shares that
+ * GPU's array and resets the slabs it uses; calls that overlap on one GPU (from
+ * any thread or stream) race and must be serialised by the caller.  Other
+ * errors as bc_compute_device.
+ */
+#define BC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+bc_status bc_compute_device_noalloc(bc_graph *g, const int32_t *sources_dev, int64_t k,
+                                    const bc_options *opt, double *bc_dev, bc_stats *stats);
+
+/*
  * Edge betweenness (the paper's tool reports node and edge BC, Sec. 1): for
  * every arc e = (v, u) of the caller's CSR, ebc[e] = sum over the listed
  * sources s and all targets t of sigma_st(e) / sigma_st, where sigma_st(e)

@@ -134,6 +134,8 @@ def _load():
         "bc_compute": ([P, P, i64, ctypes.POINTER(bc_options), ctypes.POINTER(P)], ctypes.c_int),
         "bc_compute_device": ([P, P, i64, ctypes.POINTER(bc_options), P,
                                ctypes.POINTER(bc_stats)], ctypes.c_int),
+        "bc_compute_device_noalloc": ([P, P, i64, ctypes.POINTER(bc_options), P,
+                                       ctypes.POINTER(bc_stats)], ctypes.c_int),
         "bc_compute_edges": ([P, P, i64, ctypes.POINTER(bc_options), P, P], ctypes.c_int),
         "bc_compute_edges_device": ([P, P, i64, ctypes.POINTER(bc_options), P, P,
                                      ctypes.POINTER(bc_stats)], ctypes.c_int),
@@ -248,6 +250,20 @@ def bc_compute_device(g, sources_dev_ptr: int, k: int, bc_dev_ptr: int,
     _check(_lib.bc_compute_device(g, ctypes.c_void_p(sources_dev_ptr), int(k), opt,
                                   ctypes.c_void_p(bc_dev_ptr), ctypes.byref(st)))
     return st
+
+
+def bc_compute_device_noalloc(g, sources_dev_ptr: int, k: int, bc_dev_ptr: int,
+                              options: bc_options | None = None) -> bc_stats:
+    """The batched form with its state slabs in the library's fixed device
+    array (no device allocation during the call)."""
+    st = bc_stats()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_lib.bc_compute_device_noalloc(g, ctypes.c_void_p(sources_dev_ptr), int(k), opt,
+                                          ctypes.c_void_p(bc_dev_ptr), ctypes.byref(st)))
+    return st
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # BC_NOALLOC_SCRATCH_BYTES of include/bc.h
 
 
 def bc_compute_edges(g, sources, n: int, nnz: int, options: bc_options | None = None):

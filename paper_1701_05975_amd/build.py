@@ -20,7 +20,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
 # Device code: gfx950 only; packed FP32 instructions disabled.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-SOURCES = ["kernels.hip", "interleaved.hip", "ingest.hip", "bc_api.cpp", "interleaved.cpp",
+SOURCES = ["kernels.hip", "interleaved.hip", "ingest.hip", "noalloc.hip", "bc_api.cpp", "interleaved.cpp",
            "autotune.cpp", "server.cpp"]
 
 

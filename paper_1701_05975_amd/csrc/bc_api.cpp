@@ -53,25 +53,7 @@ bc_status bc_fail(const bc_error &e)
     return e.status;
 }
 
-template <class F> static bc_status guarded(F &&f)
-{
-    try {
-        g_last_error.clear();
-        f();
-        return BC_OK;
-    } catch (const bc_error &e) {
-        return bc_fail(e);
-    } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
-        return BC_E_NOMEM;
-    } catch (const std::exception &e) {
-        g_last_error = e.what();
-        return BC_E_INTERNAL;
-    } catch (...) {
-        g_last_error = "unknown failure";
-        return BC_E_INTERNAL;
-    }
-}
+template <class F> static bc_status guarded(F &&f) { return bc_guarded(std::forward<F>(f)); }
 
 // ---------------------------------------------------------------------------
 // Device buffers
@@ -694,8 +676,8 @@ void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out)
     out = *g->host_counters;
 }
 
-static void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters &c, int64_t k,
-                       double ms, double kernel_ms, int64_t launches, bc_stats *st)
+void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters &c, int64_t k,
+                double ms, double kernel_ms, int64_t launches, bc_stats *st)
 {
     if (!st)
         return;
@@ -743,7 +725,7 @@ void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, Ba
     a.hubs = g->maxdeg > wg_deg;
 }
 
-static void check_device_errors(const DevCounters &c)
+void check_device_errors(const DevCounters &c)
 {
     if (c.err[0] & BC_ERRBIT_SOURCE)
         throw bc_error(BC_E_INVAL, "a source in the device source list is out of range");

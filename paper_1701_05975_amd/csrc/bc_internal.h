@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <new>
+#include <stdexcept>
 #include <string>
 
 #include "../../include/bc.h"
@@ -18,6 +20,30 @@ struct bc_error {
 
 void hip_check(hipError_t e, const char *what);
 void bc_set_last_error(const std::string &msg);
+// Sets the thread's last-error message from e and returns its status.
+bc_status bc_fail(const bc_error &e);
+
+// Runs f, turning any exception into a status (no exception crosses the C ABI).
+template <class F> bc_status bc_guarded(F &&f)
+{
+    try {
+        bc_set_last_error(std::string());
+        f();
+        return BC_OK;
+    } catch (const bc_error &e) {
+        return bc_fail(e);
+    } catch (const std::bad_alloc &) {
+        bc_set_last_error("host allocation failed");
+        return BC_E_NOMEM;
+    } catch (const std::exception &e) {
+        bc_set_last_error(e.what());
+        return BC_E_INTERNAL;
+    } catch (...) {
+        bc_set_last_error("unknown failure");
+        return BC_E_INTERNAL;
+    }
+}
+
 
 struct DevBuf {
     void *p = nullptr;
@@ -154,6 +180,12 @@ void create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
 // Degree-tier fields of the batched kernel's arguments.
 void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a);
 void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);
+// Status of a finished computation from its device counters (throws on an
+// out-of-range source, a tripped iteration bound or a count overflow).
+void check_device_errors(const DevCounters &c);
+// Statistics of a finished computation (st may be NULL).
+void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters &c, int64_t k,
+                double ms, double kernel_ms, int64_t launches, bc_stats *st);
 // Source-interleaved form: groups of 64 sources per sweep for n vertices, nnz
 // arcs, k sources and the given free device bytes (0: not even one fits).
 int interleaved_groups_per_sweep(int32_t n, int64_t nnz, int64_t k, size_t free_bytes);
