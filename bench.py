@@ -410,6 +410,8 @@ def main():
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--dep-mode", type=int, default=0)
     ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (16, 32)")
+    ap.add_argument("--far-buckets", type=int, default=0,
+                    help="far values: 0 auto, 1 bucket ring, 2 two-tier pile")
     ap.add_argument("--edges", action="store_true",
                     help="time node + edge betweenness (bc_compute_edges_device)")
     ap.add_argument("--interleaved-sources", type=int, default=256,
@@ -481,6 +483,10 @@ def main():
                     dep_mode=args.dep_mode or pinned.get("dep_mode", 0),
                     lds_bits=args.lds_bits or pinned.get("lds_bits", 0),
                     batch=args.batch or pinned.get("batch", 0), accumulate=args.accumulate,
+                    far_buckets=args.far_buckets or pinned.get("far_buckets", 0),
+                    expand_lane_deg=pinned.get("expand_lane_deg", 0),
+                    wave_max_deg=pinned.get("wave_max_deg", 0),
+                    wg_min_deg=pinned.get("wg_min_deg", 0),
                     stream=stream.cuda_stream)
         base.update(kw)
         return bc.make_options(**base)
@@ -490,7 +496,9 @@ def main():
     for i in range(args.warmup):
         st = run(o)
         print(f"# warmup {i}: {st.ms:.1f} ms (delta={st.delta} wg={st.wg_threads} "
-              f"lane_max={st.lane_max_deg} batch={st.batch})", file=sys.stderr, flush=True)
+              f"lane_max={st.lane_max_deg} batch={st.batch} expand_lane_deg={st.expand_lane_deg} "
+              f"wave_max_deg={st.wave_max_deg} wg_min_deg={st.wg_min_deg} "
+              f"far_buckets={st.far_buckets})", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -573,7 +581,9 @@ def main():
             "delta": last.delta, "wg_threads": last.wg_threads, "lane_max_deg": last.lane_max_deg,
             "batch": last.batch, "accumulate": last.accumulate, "dep_mode": last.dep_mode,
             "lds_vertices": last.lds_vertices,
-            "lds_bits": last.lds_bits,
+            "lds_bits": last.lds_bits, "far_buckets": last.far_buckets,
+            "expand_lane_deg": last.expand_lane_deg, "wave_max_deg": last.wave_max_deg,
+            "wg_min_deg": last.wg_min_deg,
             "reached": last.reached, "arcs_out_reached": last.arcs_out_reached,
             "dag_arcs": last.dag_arcs, "improvements": last.improvements,
             "bands": last.bands, "iterations": last.iterations,

@@ -164,7 +164,9 @@ typedef struct {
     int32_t lane_max_deg; /* count and dependency passes: vertices with at most this many
                              in-arcs (recorded predecessors) are handled by one lane, larger
                              ones by a whole 64-lane wave */
-    int32_t wg_threads;   /* batched: threads per workgroup (256, 512 or 1024) */
+    int32_t wg_threads;   /* batched: threads per workgroup (256, 512 or 1024); with batch
+                             set, a CU's LDS is shared only by the workgroups those
+                             sources need */
     int32_t autotune;     /* 1 = time candidate settings once per graph and keep the best:
                              band width, workgroup size, dependency method, lane_max_deg,
                              the expansion degree tiers and the sources in flight, each
@@ -202,6 +204,17 @@ typedef struct {
     int32_t expand_lane_deg;
     int32_t wave_max_deg;
     int32_t wg_min_deg;
+    int32_t far_buckets;  /* batched: how far values wait for their band (the near-far
+                             split of Sec. 3.2's phases).  1 = a ring of buckets of width
+                             delta, one per future band up to the maximum weight (at most
+                             128), each vertex entering a bucket only when its tentative
+                             distance drops into a lower one, so a band takes just its own
+                             bucket; bands are then aligned to multiples of delta.
+                             2 = a two-tier pile (values within 16 band widths, then the
+                             rest), rescanned at every band change.  0 = the ring when the
+                             maximum weight spans at least 16 band widths, else the pile.
+                             The ring needs head and weight packed in one arc word
+                             (bc_graph_info.packed_arcs); other graphs keep the pile */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 
@@ -225,7 +238,8 @@ typedef struct {
                                  dependency rounds and far-pile splits */
     /* the settings the computation ran with (defaults and autotuned values filled in) */
     int32_t mode, batch, delta, lane_max_deg, wg_threads, accumulate, lds_vertices, dep_mode,
-        virtual_warp, node_parallel, lds_bits, expand_lane_deg, wave_max_deg, wg_min_deg;
+        virtual_warp, node_parallel, lds_bits, expand_lane_deg, wave_max_deg, wg_min_deg,
+        far_buckets; /* far_buckets: 1 ring, 2 pile (batched form), 0 other forms */
 } bc_stats;
 
 /*
@@ -266,7 +280,7 @@ bc_status bc_compute_device(bc_graph *g, const int32_t *sources_dev, int64_t k,
  * caller still provides sources_dev[k] and bc_dev[n] (device memory).
  *
  * Sources in flight are capped by how many state slabs fit in the array; a
- * graph whose single slab (about 76 bytes per vertex plus 4 per arc) does not
+ * graph whose single slab (about 84 bytes per vertex plus 4 per arc) does not
  * fit gives BC_E_NOMEM and leaves bc_dev untouched.  Only the batched form
  * runs here: opt->mode other than BC_MODE_AUTO / BC_MODE_BATCHED, or
  * opt->autotune set, gives BC_E_INVAL.  Every call on one GPU shares that

@@ -56,7 +56,7 @@ class bc_options(ctypes.Structure):
                 ("virtual_warp", ctypes.c_int32), ("node_parallel", ctypes.c_int32),
                 ("lds_bits", ctypes.c_int32), ("expand_lane_deg", ctypes.c_int32),
                 ("wave_max_deg", ctypes.c_int32), ("wg_min_deg", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("far_buckets", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class bc_stats(ctypes.Structure):
@@ -74,7 +74,7 @@ class bc_stats(ctypes.Structure):
                 ("dep_mode", ctypes.c_int32), ("virtual_warp", ctypes.c_int32),
                 ("node_parallel", ctypes.c_int32), ("lds_bits", ctypes.c_int32),
                 ("expand_lane_deg", ctypes.c_int32), ("wave_max_deg", ctypes.c_int32),
-                ("wg_min_deg", ctypes.c_int32)]
+                ("wg_min_deg", ctypes.c_int32), ("far_buckets", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -181,7 +181,7 @@ def _ptr(a: np.ndarray):
 def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotune=0,
                  accumulate=0, lds_vertices=0, dep_mode=0, virtual_warp=0, node_parallel=0,
                  lds_bits=0, expand_lane_deg=0, wave_max_deg=0, wg_min_deg=0,
-                 stream=None) -> bc_options:
+                 far_buckets=0, stream=None) -> bc_options:
     o = bc_options()
     o.mode, o.batch, o.delta = mode, batch, delta
     o.lane_max_deg, o.wg_threads, o.autotune, o.accumulate = lane_max_deg, wg_threads, autotune, accumulate
@@ -193,6 +193,7 @@ def make_options(mode=0, batch=0, delta=0, lane_max_deg=0, wg_threads=0, autotun
     o.expand_lane_deg = expand_lane_deg
     o.wave_max_deg = wave_max_deg
     o.wg_min_deg = wg_min_deg
+    o.far_buckets = far_buckets
     o.stream = stream
     return o
 

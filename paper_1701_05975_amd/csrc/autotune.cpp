@@ -63,7 +63,8 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
     const int64_t cap = batch_cap(g);
     auto fill_for = [&](int nt, int &H) {
         int per_cu = 1;
-        batched_lds_plan(g, nt, r.accumulate == 2, o.lds_vertices, r.lds_bits, H, per_cu);
+        batched_lds_plan(g, nt, r.accumulate == 2, o.lds_vertices, r.lds_bits, H, per_cu,
+                         o.batch);
         return (int64_t)g->num_cus * per_cu;
     };
     if (!g->tuned.valid) {

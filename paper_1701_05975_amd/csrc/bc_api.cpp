@@ -496,6 +496,7 @@ SlabLayout slab_layout(int32_t n, int64_t pred_slots)
     L.qb = take(4 * nn);
     L.fa = take(4 * nn);
     L.fb = take(4 * nn);
+    L.bx = take(8 * nn); // with fa and fb: the bucket pool of the far-bucket ring
     L.oa = take(4 * nn);
     L.ob = take(4 * nn);
     L.band_off = take(4 * (nn + 2));
@@ -559,12 +560,15 @@ static size_t lds_bytes_for(int H, int bits)
 }
 
 void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
-                      int &H, int &per_cu)
+                      int &H, int &per_cu, int64_t want_slabs)
 {
-    // Workgroups per CU are set by registers; the LDS (160 KB per CU) is then
-    // split among them for the per-source distance caches.
+    // Workgroups per CU are set by registers (or by the sources in flight the
+    // caller asked for, when those fill fewer); the LDS (160 KB per CU) is
+    // then split among them for the per-source distance caches.
     const bool w16 = bits == 16;
-    const int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc, w16);
+    int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc, w16);
+    if (want_slabs > 0)
+        occ = (int)std::min<int64_t>(occ, (want_slabs + g->num_cus - 1) / g->num_cus);
     const size_t lds_cu = 160 * 1024, reserve = 2 * 1024;
     int cap = (int)((lds_cu / (size_t)std::max(occ, 1) - reserve) / (size_t)(bits / 8));
     cap &= ~1;
@@ -586,13 +590,13 @@ void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, 
 
 int64_t batch_cap(bc_graph *g)
 {
-    // keep the slabs within half of the free device memory (the graph's own
+    // keep the slabs within 60% of the free device memory (the graph's own
     // slabs count as free: a larger set replaces them)
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     const size_t stride = slab_layout(g->n, g->nnz).stride;
     const size_t have = g->batched.base.p ? (size_t)g->batched.nslabs * stride : 0;
-    const int64_t by_mem = (int64_t)((free_b + have) / 2 / std::max<size_t>(stride, 1));
+    const int64_t by_mem = (int64_t)((free_b + have) / 10 * 6 / std::max<size_t>(stride, 1));
     if (by_mem < 1)
         throw bc_error(BC_E_NOMEM, "one state slab (%zu bytes) does not fit", stride);
     return std::min<int64_t>(by_mem, 65535);
@@ -622,6 +626,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
     if (o.expand_lane_deg < 0 || o.wave_max_deg < 0 || o.wg_min_deg < 0)
         throw bc_error(BC_E_INVAL, "negative degree threshold");
+    if (o.far_buckets < 0 || o.far_buckets > 2)
+        throw bc_error(BC_E_INVAL, "far_buckets must be 0, 1 or 2");
     r.mode = o.mode == BC_MODE_PLAIN || o.mode == BC_MODE_INTERLEAVED ? o.mode : BC_MODE_BATCHED;
     r.stream = o.stream ? (hipStream_t)o.stream : g->stream;
     r.wg_threads = o.wg_threads ? o.wg_threads : 256;
@@ -643,10 +649,11 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
     r.wave_deg = std::max(r.lane_deg, o.wave_max_deg ? o.wave_max_deg : BC_DEF_WAVE_DEG);
     r.wg_deg = std::max(r.wave_deg, o.wg_min_deg ? o.wg_min_deg : BC_HUB_DEG);
     r.il_groups = (int)std::min<int64_t>(((int64_t)o.batch + 63) / 64, INT32_MAX);
+    r.far_buckets = o.far_buckets;
     int per_cu = 1;
     r.lds_bits = lds_bits_for(g, o.lds_bits);
     batched_lds_plan(g, r.wg_threads, r.accumulate == 2, o.lds_vertices, r.lds_bits,
-                     r.lds_vertices, per_cu);
+                     r.lds_vertices, per_cu, o.batch);
     const int fill = g->num_cus * per_cu;
     int64_t b = o.batch ? o.batch : fill;
     b = std::min<int64_t>(b, std::max<int64_t>(k, 1));
@@ -715,6 +722,19 @@ void fill_stats(bc_graph *g, const ResolvedOptions &r, const DevCounters &c, int
     st->expand_lane_deg = r.lane_deg;
     st->wave_max_deg = r.wave_deg;
     st->wg_min_deg = r.wg_deg;
+    int buckets = 0, nbk = 0;
+    bucket_plan(g, r, buckets, nbk);
+    st->far_buckets = r.mode == BC_MODE_BATCHED ? (buckets ? 1 : 2) : 0;
+}
+
+void bucket_plan(const bc_graph *g, const ResolvedOptions &r, int &buckets, int &nbk)
+{
+    // One bucket per band a far value can lie ahead (a value found in band b is
+    // below (b + 1) delta + w_max), plus slack; the ring pays off when the
+    // weights span many bands, where the pile would be rescanned many times.
+    const int64_t spans = ((int64_t)g->wmax + r.delta - 1) / std::max(r.delta, 1);
+    nbk = (int)std::min<int64_t>(spans + 2, BC_BUCKETS_MAX);
+    buckets = g->packed && (r.far_buckets == 1 || (r.far_buckets == 0 && spans >= 16));
 }
 
 void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a)
@@ -767,6 +787,10 @@ void launch_batched_pass(bc_graph *g, const ResolvedOptions &r, const int32_t *s
     a.lane_max = r.lane_max;
     a.stats = &c->stats;
     a.err = c->err;
+    bucket_plan(g, r, a.buckets, a.nbk);
+    // bucket pool: fa, fb and bx, contiguous in the slab
+    a.bcap = (int32_t)std::min<size_t>((L.bx + 8 * (size_t)g->n - L.fa) / 4 / (size_t)a.nbk,
+                                       (size_t)INT32_MAX);
     hip_check(hipEventRecord(g->ev_k0, st), "event");
     hip_check(launch_batched(a, g->packed, r.wg_threads, atomic_bc, nslabs, st), "batched kernel");
     hip_check(hipEventRecord(g->ev_k1, st), "event");

@@ -44,7 +44,6 @@ template <class F> bc_status bc_guarded(F &&f)
     }
 }
 
-
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -86,6 +85,7 @@ struct ResolvedOptions {
     int wave_deg = BC_DEF_WAVE_DEG; // a group of lanes up to this many, a wave above,
     int wg_deg = BC_HUB_DEG;        // the whole workgroup above this (batched form)
     int node_parallel = 0;
+    int far_buckets = 0;  // batched: 0 auto, 1 far-bucket ring, 2 two-tier pile
     int il_groups = 0;    // interleaved form: groups of 64 sources per sweep (0 = by memory)
     hipStream_t stream = nullptr;
 };
@@ -160,10 +160,12 @@ int default_delta(const bc_graph *g);
 // Width of the LDS distance entries for a requested width (0 = by graph).
 int lds_bits_for(const bc_graph *g, int requested);
 // LDS-resident distances per source and the matching workgroups per CU.
+// want_slabs > 0: the caller fixed the sources in flight, so no more workgroups
+// than those need share a CU's LDS.
 void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
-                      int &H, int &per_cu);
+                      int &H, int &per_cu, int64_t want_slabs = 0);
 ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k);
-// Most state slabs a batched launch may use (half of the free device memory,
+// Most state slabs a batched launch may use (60% of the free device memory,
 // at most 65535).
 int64_t batch_cap(bc_graph *g);
 void compute_device(bc_graph *g, const int32_t *src_dev, const int32_t *src_host, int64_t k,
@@ -177,6 +179,9 @@ void reset_device_counters(bc_graph *g, hipStream_t st);
 // stream and counters already set up).
 void create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *w, uint32_t flags, hipStream_t st, bc_graph *g);
+// Far-bucket ring of a batched launch with band width r.delta: whether it is
+// used, and its number of buckets.
+void bucket_plan(const bc_graph *g, const ResolvedOptions &r, int &buckets, int &nbk);
 // Degree-tier fields of the batched kernel's arguments.
 void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a);
 void read_device_counters(bc_graph *g, hipStream_t st, DevCounters &out);

@@ -33,6 +33,9 @@ struct BatchArgs {
     uint32_t wg_deg;              // expansion: more arcs than this -> the whole workgroup
     DevStats *stats;
     unsigned long long *err;      // [0] error bits, [1] first overflowing source index
+    // Far-bucket ring (0: the two-tier far pile): nbk buckets of width delta, each
+    // holding up to bcap vertices in the slab's far-pile memory (fa onwards).
+    int32_t buckets = 0, nbk = 0, bcap = 0;
 };
 
 // Phase machine of the plain form (device memory, one per graph).

@@ -46,6 +46,11 @@ struct WgCtl {
     unsigned long long iters;
     unsigned int bands, srounds, drounds;
     unsigned long long ticks[5]; // per-phase device time of this workgroup
+    // far-bucket ring: entries per slot, the bucket of the current band, the
+    // next non-empty one (offset from bcur, 0 = none), outer pile must be scanned
+    int bcnt[BC_BUCKETS_MAX];
+    int32_t bcur;
+    int bnext, forced;
 };
 
 // Phase timing of one workgroup: thread 0 reads the constant-rate device
@@ -58,6 +63,159 @@ __device__ __forceinline__ void phase_mark(WgCtl &C, long long &t0, int phase)
         C.ticks[phase] += (unsigned long long)(t - t0);
         t0 = t;
     }
+}
+
+// Far-bucket ring: after band C.bcur closed, the next band is the least
+// non-empty bucket, over the ring and a lower bound of the outer pile (values
+// beyond the ring, or pushes a full bucket could not take).  When the outer
+// pile may hold values of the new ring window, or a bucket overflowed, it is
+// scanned: entries of the new band's bucket join the band at once, entries of
+// later buckets in the window move into the ring (or stay, if theirs is
+// full), settled entries are dropped.  Then the ring bucket's entries move into
+// the near queue as the band [b delta, (b + 1) delta); entries whose distance
+// dropped below their bucket since (settled in an earlier band) and repeats
+// are skipped.  Returns false once no vertex is left, or when the band bound
+// trips.
+template <int NT>
+__device__ __forceinline__ bool bucket_next_band(const Slab &S, WgCtl &C, const BatchArgs &a,
+                                                 unsigned long long iter_cap)
+{
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int nbk = a.nbk;
+    const uint32_t D = a.delta;
+    // the least non-empty ring bucket in (bcur, bcur + nbk), as an offset
+    if (tid < WAVE) {
+        int found = 0;
+        for (int j0 = 1; j0 < nbk && !found; j0 += WAVE) {
+            const int j = j0 + lane;
+            const bool ne = j < nbk && C.bcnt[(int)(((uint32_t)C.bcur + j) % (uint32_t)nbk)] > 0;
+            const uint64_t m = __ballot(ne);
+            if (m)
+                found = j0 + __ffsll((unsigned long long)m) - 1;
+        }
+        if (lane == 0)
+            C.bnext = found;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t b = UINT64_MAX;
+        if (C.bnext > 0)
+            b = (uint64_t)C.bcur + (uint64_t)C.bnext;
+        if (C.outer_cnt > 0) {
+            // outer_min is at most the distance of every unsettled outer entry
+            uint64_t bo = C.outer_min / D;
+            if (bo < (uint64_t)C.bcur + 1)
+                bo = (uint64_t)C.bcur + 1;
+            if (bo < b)
+                b = bo;
+        }
+        C.bnext = b == UINT64_MAX ? -1 : 0;
+        if (b != UINT64_MAX) {
+            C.bcur = (int32_t)b;
+            C.thr_old = C.thr;
+            C.thr = sat_add_u32(0u, (b + 1) * D);
+            C.bound = sat_add_u32(0u, (b + (uint64_t)nbk) * D);
+            C.gen += 1;
+            C.band_gen = C.gen;
+            C.near_len = 0;
+            C.resplit = C.outer_cnt > 0 &&
+                        (C.forced || (uint64_t)(C.outer_min / D) < b + (uint64_t)nbk);
+            if (C.resplit) {
+                C.forced = 0;
+                C.outer_min = BC_INF;
+                C.okept_cnt = 0;
+            }
+            if (++C.iters > iter_cap)
+                C.abort = 1;
+        }
+    }
+    __syncthreads();
+    if (C.bnext < 0 || C.abort)
+        return false;
+    const uint32_t bcur = (uint32_t)C.bcur;
+    int32_t *nq = C.cur ? S.qb : S.qa;
+    if (C.resplit) {
+        const int32_t *in = C.ocur ? S.ob : S.oa;
+        int32_t *out = C.ocur ? S.oa : S.ob;
+        const int len = C.outer_cnt;
+        uint32_t kmin = BC_INF;
+        for (int base = (tid / WAVE) * WAVE; base < len; base += NT) {
+            const int i = base + lane;
+            bool keep = false, mv = false;
+            int32_t v = 0;
+            uint32_t dv = 0;
+            if (i < len) {
+                v = in[i];
+                dv = dist_get(S, v);
+                const uint32_t b = dv / D;
+                if (b == bcur) {
+                    mv = atomic_xchg_i32<WG_SCOPE>(&S.stamp[v], C.gen) != C.gen;
+                } else if (b > bcur) {
+                    keep = true;
+                    if ((uint64_t)b < (uint64_t)bcur + nbk) {
+                        const int slot = (int)(b % (uint32_t)nbk);
+                        const int k = atomicAdd(&C.bcnt[slot], 1);
+                        if (k < a.bcap) {
+                            S.fa[(size_t)slot * (size_t)a.bcap + (size_t)k] = v;
+                            keep = false;
+                        } else {
+                            C.forced = 1;
+                        }
+                    }
+                }
+                // An entry leaving the pile clears its pile flag: unlike in the
+                // two-tier pile, a vertex can need the pile again (when a lower
+                // bucket it drops into is full).  Each vertex has at most one
+                // entry in the pile at a time.
+                if (b >= bcur && !keep)
+                    __hip_atomic_fetch_and(&S.infar[v], ~2, __ATOMIC_RELAXED, WG_SCOPE);
+            }
+            if (keep)
+                kmin = dv < kmin ? dv : kmin;
+            int k = wave_alloc(&C.okept_cnt, keep);
+            if (keep)
+                out[k] = v;
+            k = wave_alloc(&C.near_len, mv);
+            if (mv)
+                nq[k] = v;
+            k = wave_alloc(&C.order_cnt, mv);
+            if (mv)
+                S.order[k] = v;
+        }
+        kmin = wave_min_u32(kmin);
+        if (lane == 0 && kmin != BC_INF)
+            atomicMin(&C.outer_min, kmin);
+        __syncthreads();
+        if (tid == 0) {
+            C.ocur ^= 1;
+            C.outer_cnt = C.okept_cnt;
+        }
+    }
+    const int slot = (int)(bcur % (uint32_t)nbk);
+    const int len = C.bcnt[slot] < a.bcap ? C.bcnt[slot] : a.bcap;
+    const int32_t *in = S.fa + (size_t)slot * (size_t)a.bcap;
+    for (int base = (tid / WAVE) * WAVE; base < len; base += NT) {
+        const int i = base + lane;
+        bool mv = false;
+        int32_t v = 0;
+        if (i < len) {
+            v = in[i];
+            if (dist_get(S, v) / D == bcur)
+                mv = atomic_xchg_i32<WG_SCOPE>(&S.stamp[v], C.gen) != C.gen;
+        }
+        int k = wave_alloc(&C.near_len, mv);
+        if (mv)
+            nq[k] = v;
+        k = wave_alloc(&C.order_cnt, mv);
+        if (mv)
+            S.order[k] = v;
+    }
+    __syncthreads();
+    if (tid == 0)
+        C.bcnt[slot] = 0;
+    __syncthreads();
+    return true;
 }
 
 // Runs the count (or dependency) rounds over the members order[b0, b1) of
@@ -93,6 +251,7 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
         rc.keys = a.ebc == nullptr;
         rc.band_gen = C.band_gen;
         rc.wave_deg = a.wave_deg;
+        rc.count_arcs = 0; // counted in the streaming pass of the next initialisation
         if (SIGMA)
             sigma_round<PACKED, WG_SCOPE, RECORD>(g, S, rc, st_arcs, st_dag);
         else
@@ -116,7 +275,7 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
     }
 }
 
-template <bool PACKED, int NT, bool ATOMIC_BC, bool W16>
+template <bool PACKED, int NT, bool ATOMIC_BC, bool W16, bool BKT>
 __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 {
     __shared__ WgCtl C;
@@ -185,12 +344,14 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         {
             // d[] of this slab is complete here (the previous source wrote its
             // LDS part back), so the previous source's reached vertices are
-            // those with a finite distance.
+            // those with a finite distance: their dependencies go into the
+            // partial sums and their out-degrees into the arc statistic, in
+            // one coalesced pass.
             const int32_t ps = C.prev_s;
             for (int v = tid; v < n; v += NT) {
-                if (!ATOMIC_BC && ps >= 0) {
-                    const uint32_t dv = S.d[v];
-                    if (dv != BC_INF && v != ps)
+                if (ps >= 0 && S.d[v] != BC_INF) {
+                    st_arcs += g.row[v + 1] - g.row[v];
+                    if (!ATOMIC_BC && v != ps)
                         S.bcp[v] += S.delta[v];
                 }
                 if (W16 || v >= S.H)
@@ -201,7 +362,11 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 S.infar[v] = 0; // far-pile and tie flags start clear
                 if (a.ebc == nullptr)
                     *key_ptr(S, v) = KEY_NONE; // no predecessor key yet
+                if (BKT)
+                    S.pred1[v] = INT32_MAX; // in no far bucket yet
             }
+            for (int j = tid; j < a.nbk; j += NT)
+                C.bcnt[j] = 0;
         }
         __syncthreads();
         if (tid == 0) {
@@ -225,7 +390,10 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             C.thr = a.delta;
             C.far_min = BC_INF;
             C.outer_min = BC_INF;
-            C.bound = sat_add_u32(a.delta, (uint64_t)OUTER_BANDS * a.delta);
+            C.bound = BKT ? sat_add_u32(0u, (uint64_t)a.nbk * a.delta)
+                                : sat_add_u32(a.delta, (uint64_t)OUTER_BANDS * a.delta);
+            C.bcur = 0;
+            C.forced = 0;
             C.band_start = 0;
             C.nbands = 0;
             C.abort = 0;
@@ -265,8 +433,14 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ec.lane_deg = a.lane_deg;
                 ec.wave_deg = a.wave_deg;
                 ec.wg_deg = a.wg_deg;
+                ec.bk = S.fa;
+                ec.bcnt = C.bcnt;
+                ec.bdelta = a.delta;
+                ec.nbk = a.nbk;
+                ec.bcap = a.bcap;
+                ec.forced = &C.forced;
                 uint32_t fmin = BC_INF, omin = BC_INF;
-                expand_pass<PACKED, WG_SCOPE>(g, S, ec, fmin, omin, st_imp);
+                expand_pass<PACKED, WG_SCOPE, BKT>(g, S, ec, fmin, omin, st_imp);
                 if (hubs) {
                     __syncthreads();
                     // the listed hubs, each by the whole workgroup
@@ -278,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                         for (uint32_t e = hb + tid; e < he; e += NT) {
                             uint32_t u, w;
                             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                            relax<WG_SCOPE>(S, ec, u, hd + w, dist_get(S, u), (uint32_t)v, fmin,
+                            relax<WG_SCOPE, BKT>(S, ec, u, hd + w, dist_get(S, u), (uint32_t)v, fmin,
                                             omin, st_imp);
                         }
                     }
@@ -330,6 +504,13 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.band_start = b1;
             }
             __syncthreads();
+            if constexpr (BKT) {
+                const bool more = bucket_next_band<NT>(S, C, a, iter_cap);
+                phase_mark(C, tmark, 4);
+                if (!more)
+                    break;
+                continue;
+            }
             if (C.far_cnt == 0 && C.outer_cnt == 0)
                 break;
             // Next band: threshold from the least far distance seen.
@@ -507,12 +688,15 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         }
         __syncthreads();
     }
-    // the last source's dependencies
-    if (!ATOMIC_BC && C.prev_s >= 0) {
+    // the last source's dependencies and arc statistic
+    if (C.prev_s >= 0) {
         const int32_t ps = C.prev_s;
         for (int v = tid; v < n; v += NT)
-            if (S.d[v] != BC_INF && v != ps)
-                S.bcp[v] += S.delta[v];
+            if (S.d[v] != BC_INF) {
+                st_arcs += g.row[v + 1] - g.row[v];
+                if (!ATOMIC_BC && v != ps)
+                    S.bcp[v] += S.delta[v];
+            }
     }
 
     // Flush per-lane statistics: one atomic per wave.
@@ -691,6 +875,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.far_q = c->fcur ? S.fb : S.fa;
         ec.far_cnt = &c->far_cnt;
         ec.bound = BC_INF; // one far pile: the whole grid scans it per band
+        ec.bk = nullptr;
         ec.outer_q = nullptr;
         ec.outer_cnt = nullptr;
         ec.huge_q = nullptr; // a hub is one wave's work here (the grid is the team)
@@ -750,6 +935,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         rc.item_err = nullptr;
         rc.perm = a.perm;
         rc.keys = 0; // the plain form records no predecessor keys
+        rc.count_arcs = 1;
         rc.band_gen = 0;
         rc.wave_deg = a.wave_deg;
         if (phase == PH_SIGMA) {
@@ -974,35 +1160,48 @@ __global__ void k_dynamic_apply(double *bc, const double *before, const double *
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <bool PACKED, int NT, bool ATOMIC, bool W16>
+template <bool PACKED, int NT, bool ATOMIC, bool W16, bool BKT>
 static void launch_batched_t(const BatchArgs &a, int nslabs, hipStream_t st)
 {
     const size_t lds = W16 ? (size_t)((a.H + 1) / 2) * 4 : (size_t)a.H * sizeof(uint32_t);
     if (lds > 48 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC, W16>,
+        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC, W16, BKT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC, W16>), dim3(nslabs), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC, W16, BKT>), dim3(nslabs), dim3(NT), lds, st,
+                       a);
 }
 
 // Every instantiation of the batched kernel: (packed arcs, threads, atomic
-// output, 16-bit LDS distances).
+// output, 16-bit LDS distances, far-bucket ring).  The ring is built for
+// packed-arc graphs only; the others keep the two-tier far pile.
 #define BC_FOR_EACH_BATCHED(X)                                                                  \
-    X(true, 256, false, false) X(true, 256, true, false) X(true, 512, false, false)            \
-    X(true, 512, true, false) X(true, 1024, false, false) X(true, 1024, true, false)           \
-    X(false, 256, false, false) X(false, 256, true, false) X(false, 512, false, false)         \
-    X(false, 512, true, false) X(false, 1024, false, false) X(false, 1024, true, false)        \
-    X(true, 256, false, true) X(true, 256, true, true) X(true, 512, false, true)               \
-    X(true, 512, true, true) X(true, 1024, false, true) X(true, 1024, true, true)              \
-    X(false, 256, false, true) X(false, 256, true, true) X(false, 512, false, true)            \
-    X(false, 512, true, true) X(false, 1024, false, true) X(false, 1024, true, true)
+    X(true, 256, false, false, false) X(true, 256, true, false, false)                         \
+    X(true, 512, false, false, false) X(true, 512, true, false, false)                         \
+    X(true, 1024, false, false, false) X(true, 1024, true, false, false)                       \
+    X(false, 256, false, false, false) X(false, 256, true, false, false)                       \
+    X(false, 512, false, false, false) X(false, 512, true, false, false)                       \
+    X(false, 1024, false, false, false) X(false, 1024, true, false, false)                     \
+    X(true, 256, false, true, false) X(true, 256, true, true, false)                           \
+    X(true, 512, false, true, false) X(true, 512, true, true, false)                           \
+    X(true, 1024, false, true, false) X(true, 1024, true, true, false)                         \
+    X(false, 256, false, true, false) X(false, 256, true, true, false)                         \
+    X(false, 512, false, true, false) X(false, 512, true, true, false)                         \
+    X(false, 1024, false, true, false) X(false, 1024, true, true, false)                       \
+    X(true, 256, false, false, true) X(true, 256, true, false, true)                           \
+    X(true, 256, false, true, true) X(true, 256, true, true, true)                             \
+    X(true, 512, false, false, true) X(true, 512, true, false, true)                           \
+    X(true, 512, false, true, true) X(true, 512, true, true, true)                             \
+    X(true, 1024, false, false, true) X(true, 1024, true, false, true)                         \
+    X(true, 1024, false, true, true) X(true, 1024, true, true, true)
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st)
 {
     const bool w16 = a.lds16 != 0;
-#define BC_CASE(P, T, A, W)                                                                     \
-    if (packed == P && nt == T && atomic_bc == A && w16 == W) {                                 \
-        launch_batched_t<P, T, A, W>(a, nslabs, st);                                            \
+    const bool bkt = a.buckets != 0;
+#define BC_CASE(P, T, A, W, B)                                                                  \
+    if (packed == P && nt == T && atomic_bc == A && w16 == W && bkt == B) {                     \
+        launch_batched_t<P, T, A, W, B>(a, nslabs, st);                                         \
         return hipGetLastError();                                                               \
     }
     BC_FOR_EACH_BATCHED(BC_CASE)
@@ -1019,13 +1218,13 @@ int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, bool w16, siz
 {
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
-#define BC_OCC(P, T, A, W)                                                                      \
-    if (packed == P && nt == T && atomic_bc == A && w16 == W) {                                 \
+#define BC_OCC(P, T, A, W, B)                                                                   \
+    if (packed == P && nt == T && atomic_bc == A && w16 == W && !B) {                           \
         if (lds_bytes > 48 * 1024)                                                              \
-            (void)hipFuncSetAttribute((const void *)k_batched<P, T, A, W>,                      \
+            (void)hipFuncSetAttribute((const void *)k_batched<P, T, A, W, B>,                   \
                                       hipFuncAttributeMaxDynamicSharedMemorySize,               \
                                       (int)lds_bytes);                                          \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A, W>, T,     \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<P, T, A, W, B>, T,  \
                                                          lds_bytes);                            \
     }
     BC_FOR_EACH_BATCHED(BC_OCC)

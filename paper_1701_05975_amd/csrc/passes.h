@@ -133,6 +133,17 @@ struct ExpandCtx {
     uint32_t lane_deg;    // adaptive mapping: at most this many arcs -> one lane,
     uint32_t wave_deg;    // at most this many -> a group of EXPAND_GROUP lanes, more -> a wave,
     uint32_t wg_deg;      // more than this (batched, huge_q set) -> the whole workgroup
+    // Far-bucket ring (batched form, relax<.., true>; else the two-tier pile above).  A far
+    // value below `bound` goes to bucket value / bdelta, slot bucket % nbk,
+    // when that bucket is lower than any the vertex was put in before (its
+    // record's pred1 word holds the least so far); a full bucket sends the
+    // vertex to the outer pile and sets *forced, so that the pile is scanned
+    // at the next band change.
+    int32_t *bk;
+    int *bcnt;
+    uint32_t bdelta;
+    int nbk, bcap;
+    int *forced;
 };
 
 // Predecessor keys (batched form).  While distances are being found, the
@@ -174,7 +185,7 @@ __device__ __forceinline__ uint64_t *key_ptr(const Slab &S, int32_t v)
 // path.
 #define EXPAND_WG_CAP 256
 
-template <int SCOPE>
+template <int SCOPE, bool BKT = false>
 __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_t u, uint32_t nd,
                                       uint32_t du, uint32_t tail, uint32_t &far_min,
                                       uint32_t &outer_min, uint64_t &nimp)
@@ -193,6 +204,7 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
             atomic_or_i32<SCOPE>(&S.infar[u], VFLAG_TIE);
     }
     bool pn = false, pm = false, pf = false, po = false;
+    int bslot = -1; // far-bucket ring: the slot u goes to
     if (imp) {
         ++nimp;
         if (nd < c.thr) {
@@ -200,11 +212,29 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
             pn = ot != c.tag_next;
             pm = ot < c.band_gen;
         } else if (nd < c.bound) {
-            far_min = nd < far_min ? nd : far_min;
-            pf = (atomic_or_i32<SCOPE>(&S.infar[u], 1) & 1) == 0;
+            if (BKT) {
+                const int32_t b = (int32_t)(nd / c.bdelta);
+                if (b < __hip_atomic_fetch_min(&S.pred1[u], b, __ATOMIC_RELAXED, SCOPE))
+                    bslot = b % c.nbk;
+            } else {
+                far_min = nd < far_min ? nd : far_min;
+                pf = (atomic_or_i32<SCOPE>(&S.infar[u], 1) & 1) == 0;
+            }
         } else {
             outer_min = nd < outer_min ? nd : outer_min;
             po = (atomic_or_i32<SCOPE>(&S.infar[u], 2) & 2) == 0;
+        }
+    }
+    if (BKT && __ballot(bslot >= 0)) {
+        if (bslot >= 0) {
+            const int k = atomicAdd(&c.bcnt[bslot], 1);
+            if (k < c.bcap) {
+                c.bk[(size_t)bslot * (size_t)c.bcap + (size_t)k] = (int32_t)u;
+            } else { // a full bucket: the outer pile keeps u until the next band change
+                *c.forced = 1;
+                outer_min = nd < outer_min ? nd : outer_min;
+                po = (atomic_or_i32<SCOPE>(&S.infar[u], 2) & 2) == 0;
+            }
         }
     }
     if (__ballot(imp)) {
@@ -227,7 +257,7 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
 
 // Fixed virtual-warp mapping (Sec. 3.4): a group of vw lanes per vertex,
 // striding over its arcs; vw = 1 is one thread per vertex, vw = 64 one wave.
-template <bool PACKED, int SCOPE>
+template <bool PACKED, int SCOPE, bool BKT = false>
 __device__ __forceinline__ void expand_pass_vw(const DevGraph &g, const Slab &S, const ExpandCtx &c,
                                uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
 {
@@ -253,17 +283,17 @@ __device__ __forceinline__ void expand_pass_vw(const DevGraph &g, const Slab &S,
         for (uint32_t e = beg + sub; e < end; e += W) {
             uint32_t u, w;
             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-            relax<SCOPE>(S, c, u, dv + w, dist_get(S, u), (uint32_t)v, far_min, outer_min, nimp);
+            relax<SCOPE, BKT>(S, c, u, dv + w, dist_get(S, u), (uint32_t)v, far_min, outer_min, nimp);
         }
     }
 }
 
-template <bool PACKED, int SCOPE>
+template <bool PACKED, int SCOPE, bool BKT = false>
 __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, const ExpandCtx &c,
                             uint32_t &far_min, uint32_t &outer_min, uint64_t &nimp)
 {
     if (c.vw > 0) {
-        expand_pass_vw<PACKED, SCOPE>(g, S, c, far_min, outer_min, nimp);
+        expand_pass_vw<PACKED, SCOPE, BKT>(g, S, c, far_min, outer_min, nimp);
         return;
     }
     const int lane = lane_id();
@@ -311,7 +341,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
 #pragma unroll
                 for (int j = 0; j < LANE_UNROLL; ++j)
                     if (e0 + j < end)
-                        relax<SCOPE>(S, c, u[j], dv + w[j], du[j], (uint32_t)v, far_min, outer_min,
+                        relax<SCOPE, BKT>(S, c, u[j], dv + w[j], du[j], (uint32_t)v, far_min, outer_min,
                                      nimp);
             }
         }
@@ -349,7 +379,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     if (e0 + G * j < me)
-                        relax<SCOPE>(S, c, u[j], md + w[j], du[j], mv, far_min, outer_min, nimp);
+                        relax<SCOPE, BKT>(S, c, u[j], md + w[j], du[j], mv, far_min, outer_min, nimp);
             }
         }
         uint64_t hm = __ballot(heavy);
@@ -363,7 +393,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE>(S, c, u, hd + w, dist_get(S, u), hv, far_min, outer_min, nimp);
+                relax<SCOPE, BKT>(S, c, u, hd + w, dist_get(S, u), hv, far_min, outer_min, nimp);
             }
         }
     }
@@ -499,6 +529,8 @@ struct RoundCtx {
                              // least this is a member of the band being counted
     uint32_t wave_deg;       // more in-arcs than this: the whole wave (else a group of
                              // EXPAND_GROUP lanes above lane_max, one lane below)
+    int count_arcs;          // add each member's out-degree to `arcs` in the first round
+                             // (the batched form counts them in its streaming pass instead)
 };
 
 __device__ __forceinline__ void report_sigma_overflow(const RoundCtx &c)
@@ -549,28 +581,21 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
         uint32_t beg = 0, end = 0;
         if (valid) {
             v = c.items[i];
-            beg = g.trow[v];
-            end = g.trow[v + 1];
-            if (c.first_round)
+            if (c.first_round && c.count_arcs)
                 arcs += g.row[v + 1] - g.row[v];
         }
         const bool is_src = valid && v == c.s;
-        if (is_src) {
-            // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
-            store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
-            if (RECORD) {
-                S.pred1[v] = -1;
-                if (end > beg)
-                    S.preds[beg] = -1;
-            }
-        }
         bool pend = false;
         // A vertex with a single recorded predecessor takes its count from it
-        // (see key_ptr); the others scan their in-arcs below.
+        // (see key_ptr) without touching its in-row; the others scan their
+        // in-arcs below.
         bool keyed = false;
         if (c.keys && valid && !is_src) {
+            // The key's distance is v's final distance: every decrease of d[v]
+            // is an improvement, and the key keeps the least of them, so the
+            // distance itself need not be read again.
             const uint64_t key = load_u64<SCOPE>(key_ptr(S, v));
-            if (!(S.infar[v] & VFLAG_TIE) && (uint32_t)(key >> 32) == dist_get(S, v)) {
+            if (!(S.infar[v] & VFLAG_TIE) && key != KEY_NONE) {
                 keyed = true;
                 const int32_t u = (int32_t)(uint32_t)key;
                 const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
@@ -588,6 +613,19 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                             __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
                     }
                 }
+            }
+        }
+        if (valid && !keyed) {
+            beg = g.trow[v];
+            end = g.trow[v + 1];
+        }
+        if (is_src) {
+            // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
+            store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
+            if (RECORD) {
+                S.pred1[v] = -1;
+                if (end > beg)
+                    S.preds[beg] = -1;
             }
         }
         const uint32_t deg = end - beg;
@@ -973,10 +1011,7 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
         if (valid) {
             w = c.items[i];
             p1 = S.pred1[w];
-            pb = g.trow[w];
-            pe = g.trow[w + 1];
             dw = load_f64<SCOPE>(&S.delta[w]);
-            sw = (double)S.sigma[w];
             if (bc && w != c.s) {
                 const int32_t o = c.perm ? c.perm[w] : w;
                 if (ATOMIC_BC)
@@ -996,7 +1031,10 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             const int k = wave_alloc(c.next_cnt, fin);
             if (fin)
                 c.next_q[k] = u;
-        } else if (valid) {
+        } else if (valid) { // the list in preds[], at w's in-row
+            pb = g.trow[w];
+            pe = g.trow[w + 1];
+            sw = (double)S.sigma[w];
             const uint32_t lim = pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
             uint32_t j = pb;
             for (; j < lim; ++j) {

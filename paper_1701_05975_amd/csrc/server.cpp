@@ -204,6 +204,15 @@ class HipExec {
         a.lane_max = lane_max_for(g);
         a.stats = &dc->stats;
         a.err = dc->err;
+        {
+            // far values: the bucket ring or the two-tier pile, as in bc_compute
+            ResolvedOptions ro;
+            ro.delta = (int)a.delta;
+            ro.far_buckets = opts_.compute.far_buckets;
+            bucket_plan(g, ro, a.buckets, a.nbk);
+            a.bcap = (int32_t)std::min<size_t>(
+                (a.L.bx + 8 * (size_t)g->n - a.L.fa) / 4 / (size_t)a.nbk, (size_t)INT32_MAX);
+        }
         const int nslabs = std::min(c->slots, k);
         hip_check(launch_batched(a, g->packed, wg_for(g), true, nslabs, st), "sweep");
         hip_check(hipMemcpyAsync(c->h_cnt, dc, sizeof(DevCounters), hipMemcpyDeviceToHost, st),

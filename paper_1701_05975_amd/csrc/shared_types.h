@@ -13,6 +13,8 @@
 #define BC_DEF_LANE_DEG 8
 #define BC_DEF_WAVE_DEG 64
 #define BC_HUB_DEG 512
+// Most buckets of the far-bucket ring (batched form).
+#define BC_BUCKETS_MAX 128
 
 // ---------------------------------------------------------------------------
 // Graph as seen by the kernels.
@@ -49,13 +51,14 @@ struct DevGraph {
 #define VREC_STAMP 0  // i32 tag of the latest near queue the vertex entered
 #define VREC_INFAR 4  // i32 bit 0: in the inner far pile; bit 1: in the outer far pile
 #define VREC_SCNT 8   // i32 shortest-path-DAG successors not yet accumulated
-#define VREC_PRED1 12 // i32 the only DAG predecessor, or -1: the list in preds[]
+#define VREC_PRED1 12 // i32 the only DAG predecessor, or -1: the list in preds[]; before the
+                      // vertex is counted, the least far bucket it was put in (bucket ring)
 #define VREC_SIGMA 16 // u64 shortest-path count (0 = not yet final in the count pass)
 #define VREC_DELTA 24 // f64 dependency (negative = not yet final in the pull pass)
 
 // Byte offsets of the slab arrays inside one slot (all 256-byte aligned).
 struct SlabLayout {
-    size_t d, rec, bcp, order, qa, qb, fa, fb, oa, ob, band_off, hdr, preds, stride;
+    size_t d, rec, bcp, order, qa, qb, fa, fb, bx, oa, ob, band_off, hdr, preds, stride;
 };
 
 // ---------------------------------------------------------------------------

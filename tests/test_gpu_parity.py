@@ -45,6 +45,11 @@ OPTION_SETS = [
     dict(lds_bits=16),
     dict(lds_bits=32),
     dict(lds_bits=16, lds_vertices=5, wg_threads=512),
+    dict(far_buckets=1),
+    dict(far_buckets=1, delta=1, wg_threads=256),
+    dict(far_buckets=1, delta=2, lds_vertices=-1, accumulate=2),
+    dict(far_buckets=2, delta=1),
+    dict(far_buckets=1, delta=1, wg_threads=512, batch=7),
 ]
 
 
@@ -349,13 +354,15 @@ def test_config_ba100k_parity_sources():
 
 def test_config_ba100k_full_launch_linearity():
     """All 100k sources in the benchmark's launch configuration: BC over all
-    sources equals the sum over two halves, and sampled sources' states in
-    that configuration match the oracle."""
+    sources equals the oracle's exact betweenness (Eq. 1, every source) and the
+    sum over two halves, and sampled sources' states in that configuration
+    match the oracle."""
     g = gg.config_graph("ba100k")
     G = bc.Graph(g)
     allsrc = np.arange(g.n, dtype=np.int32)
     opts = LAUNCH["ba100k"]
     full, st = G.bc(allsrc, **opts)
+    rel_close(full, cached_oracle_bc(g, gg.config_sources("ba100k", g), label="ba100k"), 1e-9)
     a, _ = G.bc(allsrc[: g.n // 2], **opts)
     b, _ = G.bc(allsrc[g.n // 2:], **opts)
     assert np.all(np.isfinite(full)) and np.all(full >= 0)
