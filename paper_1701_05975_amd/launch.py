@@ -10,7 +10,8 @@ LAUNCH = {
     "ba100k": dict(delta=100, wg_threads=1024, lane_max_deg=16),
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
     "grid1000": dict(delta=182, wg_threads=1024, lane_max_deg=128, batch=256),
-    "rmat22": dict(delta=3, wg_threads=1024, lane_max_deg=32),
+    "rmat22": dict(delta=2, wg_threads=1024, lane_max_deg=8, expand_lane_deg=16,
+                   wave_max_deg=64, wg_min_deg=4096),
 }
 
 # Serving run over the eight resident graphs: the Poisson arrival rate is
