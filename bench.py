@@ -189,6 +189,11 @@ def run_serving(args):
     from paper_1701_05975_amd import bc, graphgen as gg
     from paper_1701_05975_amd.launch import SERVING
 
+    # least work first across graphs, a request overdue after starve_after_s
+    # seconds first, and sweeps of 1024-thread workgroups (the batched form's
+    # setting on the large graphs)
+    serve_opts = dict(order=args.order, graph_order=1, starve_after_s=SERVING["starve_after_s"],
+                      wg_threads=args.wg or 1024)
     nreq = args.requests or SERVING["requests"]
     warm = args.serve_warmup if args.serve_warmup >= 0 else SERVING["warmup"]
     if not 0 <= warm < nreq:
@@ -204,7 +209,7 @@ def run_serving(args):
     if args.calibrate:
         # capacity: a prefix of the stream submitted at once and served closed loop
         ncal = min(nreq, 64)
-        sv = bc.Server(order=args.order)
+        sv = bc.Server(**serve_opts)
         tw = time.perf_counter()
         ts = [sv.submit(G[gi], s) for gi, s in reqs[:ncal]]
         for (gi, s), t in zip(reqs[:ncal], ts):
@@ -225,7 +230,7 @@ def run_serving(args):
     # results kept for the mix-vs-alone check: requests spread over the measured part
     keep = set(np.linspace(warm, nreq - 1, min(args.serve_checks, nreq - warm))
                .round().astype(int).tolist())
-    sv = bc.Server(order=args.order)
+    sv = bc.Server(**serve_opts)
     gaps = np.random.default_rng(201).exponential(1.0 / lam, size=nreq)
     # completions are collected (in submission order) by a second thread while
     # arrivals continue, so that finished results are released as they come
@@ -302,6 +307,9 @@ def run_serving(args):
         "data": "synthetic (seeded generators)",
         "config": {"workload": f"serving: {WORKLOADS['serving']}",
                    "order": "fewest left first" if args.order == 1 else "oldest first",
+                   "graph_order": "least work left first",
+                   "starve_after_s": serve_opts["starve_after_s"],
+                   "wg_threads": serve_opts["wg_threads"],
                    "graphs": [f"{g.name} n={g.n} m={g.m}" for g in graphs]},
     }
     print(json.dumps(rec), flush=True)

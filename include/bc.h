@@ -419,16 +419,32 @@ typedef struct {
     int64_t slab_bytes_per_sweep; /* state-slab memory of one sweep context; 0 = 1/16 of the
                                      free memory at creation */
     int32_t max_active;           /* admitted, unfinished requests; 0 = 64 */
-    int32_t sweeps_per_graph;     /* concurrent sweeps per graph; 0 = 2 */
+    int32_t sweeps_per_graph;     /* concurrent sweeps per graph; 0 = 4 (with the default
+                                     slots, one graph can then fill the GPU when alone) */
     int32_t slots_per_sweep;      /* sources in flight per sweep; 0 = a quarter of the GPU's
                                      resident workgroups, within the slab memory */
-    int32_t items_per_sweep;      /* sources per sweep; 0 = twice the slots */
+    int32_t items_per_sweep;      /* sources per sweep; 0 = the slots (each workgroup takes one
+                                     source, so a sweep ends after about one source's time
+                                     and frees its compute units for other sweeps) */
     bc_options compute;           /* delta, lane_max_deg and wg_threads of the sweeps; 0 fields
                                      take the graph's autotuned (else default) values; mode,
                                      batch, accumulate and stream are ignored */
     int32_t order;                /* which admitted request of a graph a free sweep serves
                                      first: 0 = the oldest; 1 = the one with the fewest
                                      sources left (short requests overtake long ones) */
+    int32_t graph_order;          /* which graph's sweep starts first when several wait:
+                                     0 = the graph of the oldest admitted request; 1 = the
+                                     graph whose best request has the least work left
+                                     (sources left x (n + arcs)) */
+    double gpu_share;             /* share of the GPU's resident workgroups that the sweeps in
+                                     flight may hold together (a sweep holds its slots); a
+                                     sweep beyond it waits for one to end instead of queueing
+                                     on the device behind running workgroups; 0 = 1.0,
+                                     negative = no bound */
+    double starve_after_s;        /* a request waiting this many seconds since its arrival is
+                                     served before all younger ones (oldest first), in both
+                                     orders above; bounds how long short requests can hold a
+                                     long one back; 0 = never */
 } bc_server_opts;
 
 typedef struct {

@@ -98,7 +98,9 @@ class bc_server_opts(ctypes.Structure):
     _fields_ = [("result_budget_bytes", ctypes.c_int64), ("slab_bytes_per_sweep", ctypes.c_int64),
                 ("max_active", ctypes.c_int32), ("sweeps_per_graph", ctypes.c_int32),
                 ("slots_per_sweep", ctypes.c_int32), ("items_per_sweep", ctypes.c_int32),
-                ("compute", bc_options), ("order", ctypes.c_int32)]
+                ("compute", bc_options), ("order", ctypes.c_int32),
+                ("graph_order", ctypes.c_int32), ("gpu_share", ctypes.c_double),
+                ("starve_after_s", ctypes.c_double)]
 
 
 class bc_server_stats(ctypes.Structure):
@@ -444,6 +446,7 @@ def bc_server_destroy(sv) -> None:
 
 def make_server_opts(result_budget_bytes=0, slab_bytes_per_sweep=0, max_active=0,
                      sweeps_per_graph=0, slots_per_sweep=0, items_per_sweep=0, order=0,
+                     graph_order=0, gpu_share=0.0, starve_after_s=0.0,
                      **compute) -> bc_server_opts:
     o = bc_server_opts()
     o.result_budget_bytes = result_budget_bytes
@@ -453,6 +456,9 @@ def make_server_opts(result_budget_bytes=0, slab_bytes_per_sweep=0, max_active=0
     o.slots_per_sweep = slots_per_sweep
     o.items_per_sweep = items_per_sweep
     o.order = order
+    o.graph_order = graph_order
+    o.gpu_share = gpu_share
+    o.starve_after_s = starve_after_s
     o.compute = make_options(**compute)
     return o
 

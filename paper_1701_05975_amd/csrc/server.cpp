@@ -74,6 +74,7 @@ struct SweepCtx {
 struct GraphEntry {
     bc_graph *g = nullptr;
     int64_t m = 0; // edges for throughput accounting
+    double share = 0.0; // share of the GPU's resident workgroups one sweep holds
     std::vector<std::unique_ptr<SweepCtx>> ctx;
     int fail_status = 0; // its sweep contexts could not be created: fail the sweep
     std::string fail_msg;
@@ -257,6 +258,20 @@ class HipExec {
 
     int64_t sweeps() const { return sweeps_; }
 
+    double sweep_share(int gidx)
+    {
+        GraphEntry &e = graphs_[(size_t)gidx];
+        if (e.ctx.empty())
+            try_create_contexts(e, gidx);
+        return e.share;
+    }
+
+    double source_cost(int gidx)
+    {
+        const bc_graph *g = graphs_[(size_t)gidx].g;
+        return (double)g->n + (double)g->nnz;
+    }
+
     int max_items(int gidx)
     {
         GraphEntry &e = graphs_[(size_t)gidx];
@@ -362,7 +377,7 @@ class HipExec {
         int slots = opts_.slots_per_sweep ? opts_.slots_per_sweep : std::max(32, fill / 4);
         const int64_t by_mem = (int64_t)(opts_.slab_bytes_per_sweep / std::max<size_t>(L.stride, 1));
         slots = (int)std::max<int64_t>(1, std::min<int64_t>(slots, by_mem));
-        const int nctx = opts_.sweeps_per_graph ? opts_.sweeps_per_graph : 2;
+        const int nctx = opts_.sweeps_per_graph ? opts_.sweeps_per_graph : 4;
         // at most half of the memory free now goes to this graph's contexts,
         // beyond the reserve, so that other graphs and results still fit
         size_t free_b = 0, total_b = 0;
@@ -375,7 +390,8 @@ class HipExec {
                            "%zu bytes are free",
                            g->n, L.stride, free_b);
         slots = (int)std::min<int64_t>(slots, fit);
-        const int cap = opts_.items_per_sweep ? opts_.items_per_sweep : std::max(64, 2 * slots);
+        const int cap = opts_.items_per_sweep ? opts_.items_per_sweep : slots;
+        e.share = (double)slots / (double)std::max(fill, 1);
         for (int i = 0; i < nctx; ++i) {
             auto c = std::make_unique<SweepCtx>();
             c->gidx = gidx;
@@ -424,6 +440,8 @@ struct ExecAdapter {
     OutputTable *outs;
     int free_contexts(int g) { return ex->free_contexts(g); }
     int max_items(int g) { return ex->max_items(g); }
+    double sweep_share(int g) { return ex->sweep_share(g); }
+    double source_cost(int g) { return ex->source_cost(g); }
     bool alloc_result(bcserve::Request &r)
     {
         if (!ex->alloc_result(r))
@@ -500,6 +518,9 @@ bc_status bc_server_create(const bc_server_opts *o, bc_server **out)
             throw bc_error(BC_E_INVAL, "out is NULL");
         if (o && (o->order < 0 || o->order > 1))
             throw bc_error(BC_E_INVAL, "order must be 0 (oldest first) or 1 (fewest left first)");
+        if (o && (o->graph_order < 0 || o->graph_order > 1))
+            throw bc_error(BC_E_INVAL,
+                           "graph_order must be 0 (oldest request) or 1 (least work left)");
         int count = 0;
         if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
             (void)hipGetLastError();
@@ -526,6 +547,12 @@ bc_status bc_server_create(const bc_server_opts *o, bc_server **out)
         pol.max_active = sv->opts.max_active;
         pol.max_items_per_sweep = 1 << 30; // bounded per context by its buffers below
         pol.shortest_first = sv->opts.order == 1;
+        pol.least_work_first = sv->opts.graph_order == 1;
+        if (sv->opts.starve_after_s < 0)
+            throw bc_error(BC_E_INVAL, "starve_after_s must be >= 0");
+        pol.starve_after = sv->opts.starve_after_s;
+        pol.gpu_share = sv->opts.gpu_share == 0.0 ? 1.0 : sv->opts.gpu_share < 0 ? 0.0
+                                                                                 : sv->opts.gpu_share;
         sv->sched.reset(new bcserve::Scheduler<ExecAdapter>(sv->adapter, pol));
         bc_server *raw = sv.get();
         sv->worker = std::thread([raw] { raw->loop(); });

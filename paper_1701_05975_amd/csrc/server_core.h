@@ -49,11 +49,26 @@ struct Policy {
     int max_active = 64;           // admitted, unfinished requests
     int max_items_per_sweep = 1024;
     bool shortest_first = false;   // within a graph, fewest sources left first (else oldest)
+    // Share of the GPU that sweeps in flight may hold together (the executor
+    // reports each sweep's share); 0 = no bound.  With a bound, a launched
+    // sweep finds free compute units and starts at once instead of queueing
+    // behind long-running workgroups of other sweeps.
+    double gpu_share = 0.0;
+    // Across graphs, serve first the graph whose best request has the least
+    // work left (sources left x the executor's per-source cost); else the
+    // graph of the oldest request.
+    bool least_work_first = false;
+    // A request waiting (since arrival) at least this many seconds is served
+    // before all younger ones, oldest first, in both orders above; 0 = never.
+    // It bounds how long least-work-first can hold a large request back.
+    double starve_after = 0.0;
 };
 
 // Executor interface:
 //   int  free_contexts(int graph)                 sweeps that could start now
 //   int  max_items(int graph)                     sources one sweep of the graph can take
+//   double sweep_share(int graph)                 share of the GPU one sweep holds
+//   double source_cost(int graph)                 relative cost of one source
 //   bool alloc_result(Request&)                   device buffer for the result (zeroed)
 //   void free_result(Request&)
 //   void launch(int graph, const std::vector<SweepItem>&)
@@ -90,7 +105,7 @@ template <class Exec> class Scheduler {
     {
         bool changed = collect(now);
         changed |= admit(now);
-        changed |= dispatch();
+        changed |= dispatch(now);
         return changed;
     }
 
@@ -137,6 +152,9 @@ template <class Exec> class Scheduler {
         ex_.poll(fin);
         for (auto &f : fin) {
             --inflight_sweeps_;
+            inflight_share_ -= ex_.sweep_share(f.graph);
+            if (inflight_sweeps_ == 0 || inflight_share_ < 0)
+                inflight_share_ = 0;
             for (size_t i = 0; i < f.items.size(); ++i) {
                 auto r = find(f.items[i].ticket);
                 if (!r)
@@ -197,7 +215,13 @@ template <class Exec> class Scheduler {
         return changed;
     }
 
-    bool dispatch()
+    // true if request r has waited past the starvation bound
+    bool overdue(const Request &r, double now) const
+    {
+        return pol_.starve_after > 0 && now - r.t_arrival >= pol_.starve_after;
+    }
+
+    bool dispatch(double now)
     {
         bool changed = false;
         // graphs with pending items, oldest request first
@@ -212,6 +236,39 @@ template <class Exec> class Scheduler {
             if (std::find(graphs.begin(), graphs.end(), r->graph) == graphs.end())
                 graphs.push_back(r->graph);
             ++it;
+        }
+        if (pol_.least_work_first) {
+            // each graph ranked by its best request's remaining work
+            std::map<int, double> least;
+            for (uint64_t t : order_) {
+                auto r = find(t);
+                if (!r)
+                    continue;
+                const double w = (double)((int64_t)r->sources.size() - r->next_item) *
+                                 ex_.source_cost(r->graph);
+                auto it2 = least.find(r->graph);
+                if (it2 == least.end() || w < it2->second)
+                    least[r->graph] = w;
+            }
+            std::stable_sort(graphs.begin(), graphs.end(),
+                             [&](int x, int y) { return least[x] < least[y]; });
+        }
+        if (pol_.starve_after > 0) {
+            // graphs holding an overdue request first, the one overdue longest first
+            // (order_ is in admission order, so the first overdue request of a
+            // graph is its oldest)
+            std::map<int, double> first_arrival;
+            for (uint64_t t : order_) {
+                auto r = find(t);
+                if (r && overdue(*r, now) && !first_arrival.count(r->graph))
+                    first_arrival[r->graph] = r->t_arrival;
+            }
+            std::stable_sort(graphs.begin(), graphs.end(), [&](int x, int y) {
+                const bool ox = first_arrival.count(x) > 0, oy = first_arrival.count(y) > 0;
+                if (ox != oy)
+                    return ox;
+                return ox && first_arrival[x] < first_arrival[y];
+            });
         }
         for (int gidx : graphs) {
             const int cap = std::min(pol_.max_items_per_sweep, ex_.max_items(gidx));
@@ -228,7 +285,19 @@ template <class Exec> class Scheduler {
                     return (int64_t)rx->sources.size() - rx->next_item <
                            (int64_t)ry->sources.size() - ry->next_item;
                 });
+            if (pol_.starve_after > 0)
+                std::stable_sort(serve.begin(), serve.end(), [&](uint64_t x, uint64_t y) {
+                    auto rx = find(x), ry = find(y);
+                    const bool ox = overdue(*rx, now), oy = overdue(*ry, now);
+                    if (ox != oy)
+                        return ox;
+                    return ox && rx->t_arrival < ry->t_arrival;
+                });
+            const double share = ex_.sweep_share(gidx);
             while (ex_.free_contexts(gidx) > 0) {
+                if (pol_.gpu_share > 0 && inflight_sweeps_ > 0 &&
+                    inflight_share_ + share > pol_.gpu_share + 1e-9)
+                    break; // the GPU is full: the graph waits for a sweep to end
                 std::vector<SweepItem> items;
                 for (uint64_t t : serve) {
                     auto r = find(t);
@@ -248,6 +317,7 @@ template <class Exec> class Scheduler {
                     break;
                 ex_.launch(gidx, items);
                 ++inflight_sweeps_;
+                inflight_share_ += share;
                 changed = true;
             }
         }
@@ -264,6 +334,7 @@ template <class Exec> class Scheduler {
     size_t in_use_ = 0;
     int active_ = 0;
     int inflight_sweeps_ = 0;
+    double inflight_share_ = 0.0;
     int64_t submitted_ = 0;
 };
 

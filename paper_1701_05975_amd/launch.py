@@ -18,4 +18,4 @@ LAUNCH = {
 # fixed (measured once with `python bench.py --config serving --calibrate` at
 # 0.7 of the closed-loop capacity of the stream's first 64 requests), and the
 # first `warmup` requests of the `requests` are left out of the percentiles.
-SERVING = dict(rate=0.5725, requests=512, warmup=32)
+SERVING = dict(rate=1.4331, requests=512, warmup=32, starve_after_s=5.0)

@@ -32,6 +32,8 @@ struct FakeExec {
     std::vector<int> busy = std::vector<int>(4, 0);
     int free_contexts(int g) { return 2 - busy[(size_t)g]; }
     int max_items(int) { return 16; }
+    double sweep_share(int) { return 0.25; }
+    double source_cost(int g) { return 1.0 + g; }
     bool alloc_result(Request &r)
     {
         r.out = new double[4]();
@@ -76,6 +78,9 @@ int main()
     Policy pol;
     pol.budget_bytes = 64 * 8;
     pol.max_active = 16;
+    pol.gpu_share = 1.0;           // four sweeps of a quarter each at once
+    pol.least_work_first = true;
+    pol.starve_after = 0.002;      // overdue requests reorder the queues too
     Scheduler<FakeExec> sched(ex, pol);
     std::mutex mu;
     std::condition_variable cv_work, cv_done;

@@ -17,8 +17,11 @@ struct FakeExec {
     std::vector<std::pair<int, std::vector<SweepItem>>> running;
     std::vector<Finished> ready;          // sweeps the test has finished
     int allocs = 0, alloc_fail_after = 1 << 30;
+    std::map<int, double> share, cost;   // per graph: GPU share of a sweep, cost of a source
     int free_contexts(int g) { return ctx_per_graph.count(g) ? ctx_per_graph[g] - busy[g] : 2 - busy[g]; }
     int max_items(int) { return cap; }
+    double sweep_share(int g) { return share.count(g) ? share[g] : 0.0; }
+    double source_cost(int g) { return cost.count(g) ? cost[g] : 1.0; }
     bool alloc_result(Request &r) {
         if (allocs >= alloc_fail_after) return false;
         ++allocs;
@@ -176,6 +179,57 @@ int main() {
         CHECK(sc.find(a)->phase == ReqPhase::Done && sc.find(a)->status == 0);
         CHECK(sc.find(b)->phase == ReqPhase::Failed && sc.find(b)->status == 6);
         CHECK(sc.idle());
+    }
+    // 6b. GPU share bound and least work first across graphs: graph 0 is big
+    //     (costly sources, an old long request), graph 1 small; sweeps hold half
+    //     the GPU each
+    {
+        FakeExec ex; ex.cap = 4;
+        ex.ctx_per_graph[0] = 4; ex.ctx_per_graph[1] = 4;
+        ex.share[0] = 0.5; ex.share[1] = 0.5;
+        ex.cost[0] = 100.0; ex.cost[1] = 1.0;
+        Policy p; p.budget_bytes = 1 << 20; p.gpu_share = 1.0; p.least_work_first = true;
+        Scheduler<FakeExec> sc(ex, p);
+        uint64_t big = sc.submit(0, s10.data(), 10, 8, 0.0);
+        sc.step(0.1);
+        CHECK(ex.running.size() == 2);          // the GPU holds two half sweeps
+        uint64_t small = sc.submit(1, s3.data(), 3, 8, 0.2);
+        sc.step(0.3);
+        CHECK(ex.running.size() == 2);          // full: the small request waits
+        ex.finish_oldest();
+        sc.step(0.4);
+        CHECK(ex.running.size() == 2 && ex.running.back().first == 1);  // small one goes next
+        CHECK(ex.running.back().second.size() == 3 && ex.running.back().second[0].ticket == small);
+        while (!ex.running.empty()) { ex.finish_oldest(); sc.step(1.0); }
+        CHECK(sc.find(small)->t_done <= sc.find(big)->t_done);
+        CHECK(sc.find(big)->phase == ReqPhase::Done && sc.idle());
+    }
+    // 6c. starvation bound: with least work first, a big request that has
+    //     waited past starve_after goes before a newer small one
+    {
+        FakeExec ex; ex.cap = 4;
+        ex.ctx_per_graph[0] = 4; ex.ctx_per_graph[1] = 4;
+        ex.share[0] = 1.0; ex.share[1] = 1.0;   // one sweep fills the GPU
+        ex.cost[0] = 100.0; ex.cost[1] = 1.0;
+        Policy p; p.budget_bytes = 1 << 20; p.gpu_share = 1.0; p.least_work_first = true;
+        p.starve_after = 5.0;
+        Scheduler<FakeExec> sc(ex, p);
+        uint64_t s1 = sc.submit(1, s3.data(), 3, 8, 0.0);
+        sc.step(0.0);                            // small request takes the GPU
+        uint64_t big = sc.submit(0, s10.data(), 10, 8, 0.5);
+        uint64_t s2 = sc.submit(1, s3.data(), 3, 8, 1.0);
+        ex.finish_oldest();
+        sc.step(2.0);                            // not overdue yet: the small one goes first
+        CHECK(ex.running.size() == 1 && ex.running.back().first == 1);
+        CHECK(ex.running.back().second[0].ticket == s2);
+        uint64_t s3t = sc.submit(1, s3.data(), 3, 8, 6.0);
+        ex.finish_oldest();
+        sc.step(6.0);                            // big has waited 5.5 s: it goes before s3t
+        CHECK(ex.running.size() == 1 && ex.running.back().first == 0);
+        CHECK(ex.running.back().second[0].ticket == big);
+        while (!ex.running.empty()) { ex.finish_oldest(); sc.step(7.0); }
+        CHECK(sc.find(s1)->phase == ReqPhase::Done && sc.find(s3t)->phase == ReqPhase::Done);
+        CHECK(sc.find(big)->phase == ReqPhase::Done && sc.idle());
     }
     // 7. percentile (nearest rank)
     {
