@@ -181,7 +181,7 @@ typedef struct {
                              reverse and in Kahn's order inside a band, 2 = pull over
                              out-arcs band by band in reverse */
     int32_t virtual_warp; /* frontier expansion: 0 = by degree, one lane per vertex up to 8
-                             arcs, a group of 8 lanes up to 64, a whole wave above (and in
+                             arcs, a group of 16 lanes up to 64, a whole wave above (and in
                              the batched form the whole workgroup above 512);
                              1, 2, 4, ..., 64 = a fixed group of that many lanes per vertex
                              (the warp-centric mapping of Sec. 3.4) */
@@ -195,7 +195,7 @@ typedef struct {
     /* Degree tiers of the adaptive frontier expansion (virtual_warp = 0; the
        degree-aware thread mapping of Sec. 3.4 on 64-lane wavefronts).  A queued
        vertex with d out-arcs is expanded by one lane if d <= expand_lane_deg, by a
-       group of 8 lanes if d <= wave_max_deg, else by one whole wave; in the
+       group of 16 lanes if d <= wave_max_deg, else by one whole wave; in the
        batched form a vertex with d > wg_min_deg is expanded by the whole
        workgroup after the pass.  The count pass hands vertices with more than
        wave_max_deg in-arcs to a whole wave.  0 = default (8, 64, 512); a

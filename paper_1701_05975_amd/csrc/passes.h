@@ -176,7 +176,7 @@ __device__ __forceinline__ uint64_t *key_ptr(const Slab &S, int32_t v)
 // are run-time values (BC_DEF_LANE_DEG and BC_DEF_WAVE_DEG by default); the
 // group width is fixed.
 #ifndef EXPAND_GROUP
-#define EXPAND_GROUP 8
+#define EXPAND_GROUP 16
 #endif
 // Fourth tier (batched form): a vertex with more than wg_deg arcs (default
 // BC_HUB_DEG) is expanded by every thread of the workgroup after the pass, so
