@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 S.sigma[v] = 0;
                 if (a.kahn)
                     S.scnt[v] = 0;
-                S.infar[v] = 0; // far-pile and tie flags start clear
+                S.infar[v] = 0; // far-pile flags and tie count start clear
                 if (a.ebc == nullptr)
                     *key_ptr(S, v) = KEY_NONE; // no predecessor key yet
                 if (BKT)
@@ -430,6 +430,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 ec.huge_q = hubs ? C.huge_q : nullptr;
                 ec.huge_cnt = &C.huge_cnt;
                 ec.keys = a.ebc == nullptr;
+                ec.trow = g.trow;
                 ec.lane_deg = a.lane_deg;
                 ec.wave_deg = a.wave_deg;
                 ec.wg_deg = a.wg_deg;
@@ -881,6 +882,7 @@ __global__ __launch_bounds__(256) void k_plain_step(PlainArgs a)
         ec.huge_q = nullptr; // a hub is one wave's work here (the grid is the team)
         ec.huge_cnt = nullptr;
         ec.keys = 0;
+        ec.trow = nullptr;
         ec.lane_deg = a.lane_deg;
         ec.wave_deg = a.wave_deg;
         ec.wg_deg = BC_INF;

@@ -130,6 +130,7 @@ struct ExpandCtx {
     int32_t *huge_q;      // optional: vertices with more than EXPAND_WG_DEG arcs are listed
     int *huge_cnt;        // here for the whole workgroup to expand after the pass
     int keys;             // record each vertex's (distance, predecessor) key and ties
+    const uint32_t *trow; // with keys: in-row offsets, whose slices hold the tie entries
     uint32_t lane_deg;    // adaptive mapping: at most this many arcs -> one lane,
     uint32_t wave_deg;    // at most this many -> a group of EXPAND_GROUP lanes, more -> a wave,
     uint32_t wg_deg;      // more than this (batched, huge_q set) -> the whole workgroup
@@ -148,14 +149,31 @@ struct ExpandCtx {
 
 // Predecessor keys (batched form).  While distances are being found, the
 // dependency field of a vertex (unused until its count is taken) holds the
-// least (distance << 32 | tail) over the improvements it received, and
-// VFLAG_TIE in its far-flags word marks that some relaxation matched its
-// distance at the time.  A vertex whose final distance is the key's and that
-// never saw a tie has exactly one shortest-path predecessor, the key's tail:
-// every arc that is tight for the final distances is relaxed with its tail's
-// final distance, the first such relaxation improves and any further one
-// ties, and no vertex is expanded twice at the same distance.
-#define VFLAG_TIE 4
+// least (distance << 32 | tail) over the improvements it received, and the
+// bits from TIE_SHIFT up in its far-flags word count the relaxations that
+// matched its distance at the time (ties).  A relaxation that offers v its
+// final distance comes from a tight arc whose tail is at its own final
+// distance (one from a larger tail distance offers more), and it always
+// leaves an event: exactly one of them lowers d[v] to that value, and is the
+// key, each other one is a tie.  Ties at a larger distance belong to values
+// that were improved on later.  So the key's tail and the tails of the ties
+// at the key's distance name every shortest-path predecessor, each once per
+// tight arc and per expansion of its tail at that distance: a tail improved
+// while it is being expanded can be expanded again at the same distance.
+//
+// The first TIE_MAX ties of a vertex are kept as (distance, tail) pairs in
+// its own slice of preds[] (two words each, as far as the slice holds them),
+// which the count pass reads until it writes the vertex's DAG list there.  A
+// vertex whose ties were all kept and whose predecessor tails are all
+// distinct takes its count and its DAG list from the key and those pairs
+// without reading its in-arcs; the list then names tails rather than in-row
+// positions, and VFLAG_TLIST in the far-flags word says so.  A vertex with
+// more ties, or with a tail seen twice (a second expansion, or parallel tight
+// arcs: the pairs cannot tell these apart), scans its in-arcs.
+#define VFLAG_TLIST 4
+#define VFLAG_SCAN 8 // the count pass found a repeated tail: v scans in every round
+#define TIE_SHIFT 4
+#define TIE_MAX 7
 #define KEY_NONE (~0ull)
 
 __device__ __forceinline__ uint64_t *key_ptr(const Slab &S, int32_t v)
@@ -200,8 +218,21 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
         if (imp)
             __hip_atomic_fetch_min(key_ptr(S, (int32_t)u), (uint64_t)nd << 32 | tail,
                                    __ATOMIC_RELAXED, SCOPE);
-        if (tie)
-            atomic_or_i32<SCOPE>(&S.infar[u], VFLAG_TIE);
+        // counting stops past TIE_MAX (beyond it a vertex scans anyway), so
+        // the count stays below TIE_MAX + 2 + the threads of the workgroup
+        if (tie && ((uint32_t)__hip_atomic_load(&S.infar[u], __ATOMIC_RELAXED, SCOPE) >>
+                    TIE_SHIFT) <= TIE_MAX) {
+            const uint32_t t = (uint32_t)__hip_atomic_fetch_add(&S.infar[u], 1 << TIE_SHIFT,
+                                                                __ATOMIC_RELAXED, SCOPE) >>
+                               TIE_SHIFT;
+            if (t < TIE_MAX) {
+                const uint32_t tb = c.trow[u], te = c.trow[u + 1];
+                if (tb + 2 * (t + 1) <= te) {
+                    S.preds[tb + 2 * t] = (int32_t)nd;
+                    S.preds[tb + 2 * t + 1] = (int32_t)tail;
+                }
+            }
+        }
     }
     bool pn = false, pm = false, pf = false, po = false;
     int bslot = -1; // far-bucket ring: the slot u goes to
@@ -569,6 +600,109 @@ __device__ __forceinline__ void count_if_same_band(const DevGraph &g, const Slab
     }
 }
 
+// A DAG list entry for tail t (tails, not in-row positions: VFLAG_TLIST):
+// a tail in the band being counted is stored as -(t + 2) and gains a
+// pending successor.
+template <int SCOPE>
+__device__ __forceinline__ int32_t tail_entry(const Slab &S, const RoundCtx &c, int32_t t)
+{
+    if (S.stamp[t] < c.band_gen)
+        return t;
+    __hip_atomic_fetch_add(&S.scnt[t], 1, __ATOMIC_RELAXED, SCOPE);
+    return -(t + 2);
+}
+
+// The count of v from its key and kept ties (see key_ptr), without reading
+// its in-arcs.  Returns false when v has to scan them (a tie was not kept,
+// or a tail is seen twice);
+// sets pend when a predecessor is not counted yet.  The key's distance is v's
+// final distance: every decrease of d[v] is an improvement and the key keeps
+// the least of them.
+template <int SCOPE, bool RECORD>
+__device__ __forceinline__ bool keyed_count(const DevGraph &g, const Slab &S, const RoundCtx &c,
+                                            int32_t v, bool &pend, uint64_t &dag)
+{
+    const uint64_t key = load_u64<SCOPE>(key_ptr(S, v));
+    const int32_t fl = S.infar[v];
+    const uint32_t nt = (uint32_t)fl >> TIE_SHIFT;
+    if (key == KEY_NONE || nt > TIE_MAX || (fl & VFLAG_SCAN))
+        return false;
+    uint32_t tb = 0, te = 0;
+    if (nt > 0) {
+        tb = g.trow[v];
+        te = g.trow[v + 1];
+        if (tb + 2 * nt > te)
+            return false;
+    }
+    const uint32_t dk = (uint32_t)(key >> 32);
+    const int32_t u0 = (int32_t)(uint32_t)key;
+    // A tail seen twice: scan, in this round and in any later one (a scan
+    // that has to wait for a predecessor has already written over the pairs).
+    bool twice = false;
+    for (uint32_t i = 0; i < nt && !twice; ++i) {
+        if ((uint32_t)S.preds[tb + 2 * i] != dk)
+            continue;
+        const int32_t t = S.preds[tb + 2 * i + 1];
+        twice = t == u0;
+        for (uint32_t j = 0; j < i && !twice; ++j)
+            twice = (uint32_t)S.preds[tb + 2 * j] == dk && S.preds[tb + 2 * j + 1] == t;
+    }
+    if (twice) {
+        S.infar[v] = fl | VFLAG_SCAN;
+        return false;
+    }
+    uint64_t acc = load_u64<SCOPE>(&S.sigma[u0]);
+    bool ready = acc != 0, ovf = false;
+    uint32_t m = 0; // ties at the final distance
+    for (uint32_t i = 0; i < nt && ready; ++i) {
+        if ((uint32_t)S.preds[tb + 2 * i] != dk)
+            continue;
+        const uint64_t su = load_u64<SCOPE>(&S.sigma[S.preds[tb + 2 * i + 1]]);
+        if (su == 0) {
+            ready = false;
+        } else {
+            const uint64_t x = acc + su;
+            ovf |= x < acc;
+            acc = x;
+            ++m;
+        }
+    }
+    if (!ready) {
+        pend = true; // the pairs stay for the next round
+        return true;
+    }
+    if (ovf) {
+        report_sigma_overflow(c);
+        acc = ~0ull;
+    }
+    store_u64<SCOPE>(&S.sigma[v], acc);
+    store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
+    dag += 1 + m;
+    if (RECORD) {
+        if (m == 0) { // one predecessor: in the record, no DAG list
+            const int32_t e = tail_entry<SCOPE>(S, c, u0);
+            S.pred1[v] = e;
+        } else {
+            // The list overwrites the pairs from the front: the j-th tail goes
+            // to slot j <= i + 1 after pair i (slots 2i, 2i + 1) has been read,
+            // so no pair is overwritten before it is read.
+            uint32_t j = 1;
+            for (uint32_t i = 0; i < nt; ++i) {
+                const uint32_t di = (uint32_t)S.preds[tb + 2 * i];
+                const int32_t t = S.preds[tb + 2 * i + 1];
+                if (di == dk)
+                    S.preds[tb + j++] = tail_entry<SCOPE>(S, c, t);
+            }
+            S.preds[tb] = tail_entry<SCOPE>(S, c, u0);
+            if (tb + j < te)
+                S.preds[tb + j] = -1;
+            S.pred1[v] = -1;
+            S.infar[v] = fl | VFLAG_TLIST;
+        }
+    }
+    return true;
+}
+
 template <bool PACKED, int SCOPE, bool RECORD>
 __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, const RoundCtx &c, uint64_t &arcs,
                             uint64_t &dag)
@@ -586,35 +720,12 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
         }
         const bool is_src = valid && v == c.s;
         bool pend = false;
-        // A vertex with a single recorded predecessor takes its count from it
-        // (see key_ptr) without touching its in-row; the others scan their
-        // in-arcs below.
+        // A vertex whose predecessors are known from its key and kept ties
+        // takes its count from them (see key_ptr) without reading its
+        // in-arcs; the others scan their in-arcs below.
         bool keyed = false;
-        if (c.keys && valid && !is_src) {
-            // The key's distance is v's final distance: every decrease of d[v]
-            // is an improvement, and the key keeps the least of them, so the
-            // distance itself need not be read again.
-            const uint64_t key = load_u64<SCOPE>(key_ptr(S, v));
-            if (!(S.infar[v] & VFLAG_TIE) && key != KEY_NONE) {
-                keyed = true;
-                const int32_t u = (int32_t)(uint32_t)key;
-                const uint64_t su = load_u64<SCOPE>(&S.sigma[u]);
-                const bool same = S.stamp[u] >= c.band_gen;
-                if (su == 0) {
-                    pend = true;
-                } else {
-                    store_u64<SCOPE>(&S.sigma[v], su);
-                    store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
-                    dag += 1;
-                    if (RECORD) {
-                        // in the record: no DAG list to write or read
-                        S.pred1[v] = same ? -(u + 2) : u;
-                        if (same)
-                            __hip_atomic_fetch_add(&S.scnt[u], 1, __ATOMIC_RELAXED, SCOPE);
-                    }
-                }
-            }
-        }
+        if (c.keys && valid && !is_src)
+            keyed = keyed_count<SCOPE, RECORD>(g, S, c, v, pend, dag);
         if (valid && !keyed) {
             beg = g.trow[v];
             end = g.trow[v + 1];
@@ -1035,14 +1146,16 @@ __device__ __forceinline__ void kahn_step(const DevGraph &g, const Slab &S, cons
             pb = g.trow[w];
             pe = g.trow[w + 1];
             sw = (double)S.sigma[w];
-            const uint32_t lim = pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
+            // a list of tails (at most TIE_MAX + 1) is walked by the lane whole
+            const bool tails = (S.infar[w] & VFLAG_TLIST) != 0;
+            const uint32_t lim = !tails && pe - pb > (uint32_t)c.lane_max ? pb + c.lane_max : pe;
             uint32_t j = pb;
             for (; j < lim; ++j) {
                 const int32_t raw = S.preds[j];
                 if (raw == -1)
                     break;
                 const int32_t pos = raw < 0 ? -(raw + 2) : raw;
-                const int32_t u = pred_vertex<PACKED>(g, pos);
+                const int32_t u = tails ? pos : pred_vertex<PACKED>(g, pos);
                 const double term = (double)S.sigma[u] / sw * (1.0 + dw);
                 if (c.ebc) // the term is the source's dependency on the arc u -> w
                     unsafeAtomicAdd(&c.ebc[c.emap[pos]], term);

@@ -316,6 +316,55 @@ def test_directed_sinks_and_parallel_arcs():
     assert int(sg[1]) == 2 and int(sg[4]) == 4
 
 
+def _tie_graphs():
+    """Graphs where many vertices have several shortest-path predecessors:
+    weights 1-2 with parallel arcs (equal and unequal weights) and self-loops,
+    unit-weight layers of 1-12 vertices joined completely (so predecessor
+    counts fall on both sides of what a vertex can keep without scanning,
+    in-degree 2 and 3 included), and a unit grid (binomial counts)."""
+    rng = np.random.default_rng(11)
+    n = 3000
+    src = rng.integers(0, n, 30000)
+    dst = rng.integers(0, n, 30000)
+    w = rng.integers(1, 3, 30000)
+    dup = rng.choice(30000, 4500, replace=False)
+    unq = rng.choice(30000, 1500, replace=False)
+    src = np.concatenate([src, src[dup], src[unq]])
+    dst = np.concatenate([dst, dst[dup], dst[unq]])
+    w = np.concatenate([w, w[dup], w[unq] + 1])
+    multi = gg.csr_from_arcs(n, src, dst, w, directed=True, name="ties-multi")
+    eu, ev = [], []
+    nxt = 1
+    for chain in range(80):
+        prev = [0]
+        for layer in range(6):
+            size = int(rng.integers(1, 13))
+            cur = list(range(nxt, nxt + size))
+            nxt += size
+            for a in prev:
+                for b in cur:
+                    eu.append(a)
+                    ev.append(b)
+            prev = cur
+    layers = gg.undirected_from_edges(nxt, eu, ev, np.ones(len(eu), np.int64), name="ties-layers")
+    return [multi, layers, gg.unit_grid(30, 30)]
+
+
+@pytest.mark.parametrize("which", [0, 1, 2], ids=["multi", "layers", "grid30"])
+def test_many_tight_predecessors(which):
+    # the count pass's key-and-ties shortcut against in-arc scans, every option set
+    g = _tie_graphs()[which]
+    G = bc.Graph(g)
+    want = oracle.oracle_bc(g, np.arange(g.n))
+    for opts in OPTION_SETS:
+        got, _ = G.bc(None, **opts)
+        rel_close(got, want, 1e-9)
+    for s in (0, 1, g.n // 2, g.n - 1):
+        check_state(g, G, s)
+        check_state(g, G, s, far_buckets=1, delta=1)
+    G.close()
+
+
 def test_device_entry_point_with_torch_tensors():
     torch = pytest.importorskip("torch")
     g = gg.ba_graph(3000, 3, 1, 50, seed=5)
