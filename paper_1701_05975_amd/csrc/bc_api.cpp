@@ -430,8 +430,19 @@ static void create_graph(int32_t n, int64_t nnz, const int64_t *row_ptr, const i
     upload(g->twt, L.twt, "upload in-arc weights");
     upload(g->emap, L.emap, "upload arc map");
     g->edges_ready = L.edges;
-    hip_check(hipStreamSynchronize(g->stream), "graph upload");
+    set_inarc_bound(g.get(), g->stream);
     *out = g.release();
+}
+
+void set_inarc_bound(bc_graph *g, hipStream_t st)
+{
+    DevBuf b;
+    b.alloc(sizeof(int));
+    int v = 0;
+    hip_check(launch_inarc_bound(g->view().trow, g->n, (int *)b.p, st), "in-arc bound");
+    hip_check(hipMemcpyAsync(&v, b.p, sizeof v, hipMemcpyDeviceToHost, st), "in-arc bound");
+    hip_check(hipStreamSynchronize(st), "graph upload");
+    g->n_act = v;
 }
 
 DevGraph bc_graph::view() const
@@ -450,6 +461,7 @@ DevGraph bc_graph::view() const
         d.twt = d.wt;
     }
     d.n = n;
+    d.n_act = n_act;
     d.wshift = wshift;
     d.wmask = wmask;
     return d;

@@ -104,6 +104,7 @@ struct bc_graph {
     bool directed = false;
     int32_t wmax = 1;
     int32_t maxdeg = 0;
+    int32_t n_act = 0; // vertices from here on have no in-arcs (see DevGraph)
     int wbytes = 1;
     double avg_deg = 0.0, wmean = 1.0;
     bool packed = false;
@@ -179,6 +180,9 @@ void reset_device_counters(bc_graph *g, hipStream_t st);
 // stream and counters already set up).
 void create_graph_device(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *w, uint32_t flags, hipStream_t st, bc_graph *g);
+// Sets g->n_act from g's device in-row offsets (the last step of both
+// ingest paths; waits for stream st).
+void set_inarc_bound(bc_graph *g, hipStream_t st);
 // Far-bucket ring of a batched launch with band width r.delta: whether it is
 // used, and its number of buckets.
 void bucket_plan(const bc_graph *g, const ResolvedOptions &r, int &buckets, int &nbk);

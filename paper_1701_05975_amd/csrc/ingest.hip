@@ -720,5 +720,5 @@ void create_graph_device(int32_t n, int64_t nnz64, const int64_t *row_ptr, const
         hip_check(hipGetLastError(), "edge map");
     }
     g->edges_ready = want_edges;
-    hip_check(hipStreamSynchronize(st), "device ingest");
+    set_inarc_bound(g, st);
 }

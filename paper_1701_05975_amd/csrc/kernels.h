@@ -81,6 +81,8 @@ hipError_t launch_plain_steps(const PlainArgs &a, bool packed, int grid, int pai
                               hipStream_t st);
 hipError_t launch_plain_clear_infar(const PlainArgs &a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t st);
+// *out = one past the last vertex v with trow[v + 1] > trow[v] (0 if none)
+hipError_t launch_inarc_bound(const uint32_t *trow, int32_t n, int *out, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
                            hipStream_t st);
 hipError_t launch_slab_reset(char *slab_base, const SlabLayout &L, int nslabs, int n,

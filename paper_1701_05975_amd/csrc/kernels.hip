@@ -346,9 +346,12 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
             // LDS part back), so the previous source's reached vertices are
             // those with a finite distance: their dependencies go into the
             // partial sums and their out-degrees into the arc statistic, in
-            // one coalesced pass.
+            // one coalesced pass.  After a completed source the vertices
+            // without in-arcs (from g.n_act on) are untouched but for that
+            // source itself, so only [0, n_act) and the source are visited;
+            // the launch's first source, and one after an abort, visit all.
             const int32_t ps = C.prev_s;
-            for (int v = tid; v < n; v += NT) {
+            auto reset = [&](int v) {
                 if (ps >= 0 && S.d[v] != BC_INF) {
                     st_arcs += g.row[v + 1] - g.row[v];
                     if (!ATOMIC_BC && v != ps)
@@ -364,7 +367,12 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                     *key_ptr(S, v) = KEY_NONE; // no predecessor key yet
                 if (BKT)
                     S.pred1[v] = INT32_MAX; // in no far bucket yet
-            }
+            };
+            const int lim = ps >= 0 ? g.n_act : n;
+            for (int v = tid; v < lim; v += NT)
+                reset(v);
+            if (ps >= lim && tid == 0)
+                reset(ps);
             for (int j = tid; j < a.nbk; j += NT)
                 C.bcnt[j] = 0;
         }
@@ -689,15 +697,18 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         }
         __syncthreads();
     }
-    // the last source's dependencies and arc statistic
+    // the last source's dependencies and arc statistic (it reached no vertex
+    // without in-arcs but itself)
     if (C.prev_s >= 0) {
         const int32_t ps = C.prev_s;
-        for (int v = tid; v < n; v += NT)
+        for (int v = tid; v < g.n_act; v += NT)
             if (S.d[v] != BC_INF) {
                 st_arcs += g.row[v + 1] - g.row[v];
                 if (!ATOMIC_BC && v != ps)
                     S.bcp[v] += S.delta[v];
             }
+        if (ps >= g.n_act && tid == 0)
+            st_arcs += g.row[ps + 1] - g.row[ps];
     }
 
     // Flush per-lane statistics: one atomic per wave.
@@ -1064,6 +1075,21 @@ __global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t value)
         p[i] = value;
 }
 
+// One past the last vertex with an in-arc (0 if none): *out starts at 0.
+__global__ void k_inarc_bound(const uint32_t *trow, int32_t n, int *out)
+{
+    int last = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (trow[v + 1] > trow[v])
+            last = v + 1;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(last, o);
+        last = y > last ? y : last;
+    }
+    if (lane_id() == 0 && last > 0)
+        atomicMax(out, last);
+}
+
 __global__ void k_fill_u64(unsigned long long *p, size_t count, unsigned long long value)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
@@ -1300,6 +1326,18 @@ hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_inarc_bound(const uint32_t *trow, int32_t n, int *out, hipStream_t st)
+{
+    hipError_t e = launch_fill_u32((uint32_t *)out, 1, 0u, st);
+    if (e != hipSuccess || n <= 0)
+        return e;
+    int blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_inarc_bound, dim3(blocks), dim3(256), 0, st, trow, n, out);
     return hipGetLastError();
 }
 

@@ -33,6 +33,8 @@ struct DevGraph {
     const uint32_t *tarc;
     const int32_t *twt;
     int32_t n;
+    int32_t n_act; // vertices from n_act on have no in-arcs: no source reaches them
+                   // (each is reached only as a source itself)
     uint32_t wshift;
     uint32_t wmask;
 };

@@ -365,6 +365,54 @@ def test_many_tight_predecessors(which):
     G.close()
 
 
+def _emitters_graph(renumber_hint):
+    """A directed core of 300 vertices and 200 emitters (out-arcs only) placed
+    at the top ids, so the vertices without in-arcs are a suffix whether or not
+    the graph is renumbered; with renumber_hint a few core hubs make the
+    in-degrees skewed enough to be renumbered."""
+    rng = np.random.default_rng(31 + renumber_hint)
+    core, em = 300, 200
+    src = list(rng.integers(0, core, 2400))
+    dst = list(rng.integers(0, core, 2400))
+    for e in range(core, core + em):
+        k = int(rng.integers(1, 6))
+        src += [e] * k
+        dst += list(rng.integers(0, core, k))
+    if renumber_hint:
+        for hub in (7, 123, 250):
+            src += list(rng.integers(0, core + em, 400))
+            dst += [hub] * 400
+    src, dst = np.array(src), np.array(dst)
+    keep = src != dst
+    w = rng.integers(1, 20, int(keep.sum()))
+    return gg.csr_from_arcs(core + em, src[keep], dst[keep], w, directed=True,
+                            name=f"emitters{renumber_hint}")
+
+
+@pytest.mark.parametrize("hint", [0, 1])
+def test_vertices_without_inarcs(hint):
+    # a source's initialisation skips the vertices no source can reach (no
+    # in-arcs) once the slab is in its initial state there: long runs of
+    # sources per slab mixing emitters and core vertices, host and device ingest
+    torch = pytest.importorskip("torch")
+    g = _emitters_graph(hint)
+    want = oracle.oracle_bc(g, np.arange(g.n))
+    rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int64)).cuda()
+    col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(g.w, dtype=np.int32)).cuda()
+    torch.cuda.synchronize()
+    for G in (bc.Graph(g), bc.Graph.from_device(g, rp, col, w,
+                                                stream=torch.cuda.current_stream().cuda_stream)):
+        srcs = np.random.default_rng(5).permutation(g.n).astype(np.int32)
+        for opts in (dict(batch=3), dict(batch=1, far_buckets=1), dict(batch=2, accumulate=2),
+                     dict(batch=5, wg_threads=256, lds_vertices=-1)):
+            got, st = G.bc(srcs, **opts)
+            rel_close(got, want, 1e-9)
+        for s in (0, 299, 300, 450, g.n - 1):
+            check_state(g, G, s)
+        G.close()
+
+
 def test_device_entry_point_with_torch_tensors():
     torch = pytest.importorskip("torch")
     g = gg.ba_graph(3000, 3, 1, 50, seed=5)
