@@ -356,21 +356,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(config: str):
+def profiled_traffic(config: str, key: str = "traffic_bytes_per_launch"):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this workload, or None when the kernel sources changed since."""
+    this workload (FETCH_SIZE scaled by the copy calibration, plus WRITE_SIZE;
+    with key "traffic_unscaled_bytes_per_launch" the raw FETCH_SIZE, which
+    counts 64 bytes per request), or None when the kernel sources changed
+    since."""
     path = os.path.join(HERE, "profiles", f"k_batched_{config}.md")
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith(("|", "#")):
-            key, _, val = line.partition(":")
-            fields[key.strip()] = val.strip()
+            name, _, val = line.partition(":")
+            fields[name.strip()] = val.strip()
     if fields.get("kernel_source_hash") != kernel_source_hash():
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
 
@@ -558,6 +561,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": profiled_traffic(args.config),
+        "traffic_unscaled": profiled_traffic(args.config, "traffic_unscaled_bytes_per_launch"),
         "kernel": "k_batched",
         "kernel_ms": round(kernel_ms, 3),
         "algo_bytes_per_launch": last.algo_bytes,
