@@ -444,7 +444,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--dep-mode", type=int, default=0)
-    ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (16, 32)")
+    ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (8, 16, 32)")
     ap.add_argument("--far-buckets", type=int, default=0,
                     help="far values: 0 auto, 1 bucket ring, 2 two-tier pile")
     ap.add_argument("--edges", action="store_true",

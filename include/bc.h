@@ -189,9 +189,14 @@ typedef struct {
                              Sec. 3.3); 1 = over every vertex, expanding those queued
                              (node-parallel, Alg. 2) -- for comparison only */
     int32_t lds_bits;     /* batched: width of the LDS distance entries: 0 = auto (16 for
-                             graphs renumbered by in-degree, else 32), 16 or 32.  With 16 the
+                             graphs renumbered by in-degree, else 32), 8, 16 or 32.  With 16 the
                              cache holds twice the vertices; distances of 65535 and more of
-                             those vertices are kept in device memory instead */
+                             those vertices are kept in device memory instead.  With 8 (packed
+                             arcs; else 16 is used) it holds four times the vertices, each as
+                             an offset into a 253-wide window that follows the bands: settled
+                             vertices below the window and values beyond it are kept in
+                             device memory.  Suits graphs whose arc weights are about the
+                             window's width or less */
     /* Degree tiers of the adaptive frontier expansion (virtual_warp = 0; the
        degree-aware thread mapping of Sec. 3.4 on 64-lane wavefronts).  A queued
        vertex with d out-arcs is expanded by one lane if d <= expand_lane_deg, by a

@@ -559,6 +559,8 @@ int default_delta(const bc_graph *g)
 
 int lds_bits_for(const bc_graph *g, int requested)
 {
+    if (requested == 8)
+        return g->packed ? 8 : 16; // 8-bit entries are built for packed arcs only
     if (requested == 16 || requested == 32)
         return requested;
     // Graphs renumbered for skewed in-degrees are small-world: their distances
@@ -566,10 +568,7 @@ int lds_bits_for(const bc_graph *g, int requested)
     return g->renumbered ? 16 : 32;
 }
 
-static size_t lds_bytes_for(int H, int bits)
-{
-    return bits == 16 ? (size_t)((H + 1) / 2) * 4 : (size_t)H * 4;
-}
+static size_t lds_bytes_for(int H, int bits) { return batched_lds_bytes(H, bits); }
 
 void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, int bits,
                       int &H, int &per_cu, int64_t want_slabs)
@@ -577,25 +576,24 @@ void batched_lds_plan(const bc_graph *g, int nt, bool atomic_bc, int requested, 
     // Workgroups per CU are set by registers (or by the sources in flight the
     // caller asked for, when those fill fewer); the LDS (160 KB per CU) is
     // then split among them for the per-source distance caches.
-    const bool w16 = bits == 16;
-    int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc, w16);
+    int occ = batched_blocks_per_cu(g->packed, nt, atomic_bc, bits);
     if (want_slabs > 0)
         occ = (int)std::min<int64_t>(occ, (want_slabs + g->num_cus - 1) / g->num_cus);
     const size_t lds_cu = 160 * 1024, reserve = 2 * 1024;
     int cap = (int)((lds_cu / (size_t)std::max(occ, 1) - reserve) / (size_t)(bits / 8));
-    cap &= ~1;
+    cap &= ~3;
     if (requested < 0)
         H = 0;
     else if (requested > 0)
         H = std::min(requested, g->n);
     else
         H = std::min(cap, g->n);
-    per_cu = H > 0 ? batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, w16,
+    per_cu = H > 0 ? batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, bits,
                                                lds_bytes_for(H, bits))
                    : occ;
     if (per_cu < 1) {
         H = std::min(cap, g->n);
-        per_cu = batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, w16, lds_bytes_for(H, bits));
+        per_cu = batched_blocks_per_cu_lds(g->packed, nt, atomic_bc, bits, lds_bytes_for(H, bits));
     }
     per_cu = std::max(per_cu, 1);
 }
@@ -632,8 +630,8 @@ ResolvedOptions resolve_options(bc_graph *g, const bc_options *opt, int64_t k)
         throw bc_error(BC_E_INVAL, "unknown dependency mode %d", o.dep_mode);
     if (o.virtual_warp < 0 || o.virtual_warp > 64 || (o.virtual_warp & (o.virtual_warp - 1)))
         throw bc_error(BC_E_INVAL, "virtual_warp must be 0 or a power of two up to 64");
-    if (o.lds_bits != 0 && o.lds_bits != 16 && o.lds_bits != 32)
-        throw bc_error(BC_E_INVAL, "lds_bits must be 0, 16 or 32");
+    if (o.lds_bits != 0 && o.lds_bits != 8 && o.lds_bits != 16 && o.lds_bits != 32)
+        throw bc_error(BC_E_INVAL, "lds_bits must be 0, 8, 16 or 32");
     if (o.node_parallel < 0 || o.node_parallel > 1)
         throw bc_error(BC_E_INVAL, "node_parallel must be 0 or 1");
     if (o.expand_lane_deg < 0 || o.wave_max_deg < 0 || o.wg_min_deg < 0)
@@ -788,7 +786,7 @@ void launch_batched_pass(bc_graph *g, const ResolvedOptions &r, const int32_t *s
     a.iperm = g->iperm_dev();
     a.perm = g->perm_dev();
     a.H = r.lds_vertices;
-    a.lds16 = r.lds_bits == 16;
+    a.lds_bits = r.lds_bits;
     set_tier_args(g, r.lane_deg, r.wave_deg, r.wg_deg, a);
     a.kahn = r.dep_mode == 1 ? 1 : 0;
     a.vw = r.vw;

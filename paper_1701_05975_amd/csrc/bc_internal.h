@@ -78,7 +78,7 @@ struct ResolvedOptions {
     int accumulate = 1;
     int autotune = 0;
     int lds_vertices = 0; // H: distances kept in LDS per source
-    int lds_bits = 32;    // width of an LDS distance entry (16 or 32)
+    int lds_bits = 32;    // width of an LDS distance entry (8, 16 or 32)
     int dep_mode = 1;     // 1 recorded DAG (Kahn), 2 band pulls
     int vw = 0;           // expansion lanes per vertex (0 adaptive)
     int lane_deg = BC_DEF_LANE_DEG; // adaptive expansion: one lane up to this many arcs,

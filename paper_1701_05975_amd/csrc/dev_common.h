@@ -50,6 +50,8 @@ struct Slab {
     uint32_t *ld;      // distances of vertices 0 .. H-1 kept in LDS (batched form)
     int32_t H;         // number of LDS-resident distances (0 = none)
     int32_t w16;       // LDS entries are 16-bit; LDS16_FAR = look in d[]
+    int32_t w8;        // LDS entries are 8-bit, relative to base8 (see LDS8_WIN)
+    uint32_t base8;    // 8-bit entries: the window's base (a band threshold)
     int32_t *preds;    // in-row positions of v's DAG in-arcs, at preds[trow[v] ...],
                        // ended by -1 when fewer than the in-degree
 };
@@ -73,6 +75,8 @@ __device__ __forceinline__ Slab slab_at(char *base, const SlabLayout &L, int slo
     s.ld = nullptr;
     s.H = 0;
     s.w16 = 0;
+    s.w8 = 0;
+    s.base8 = 0;
     s.preds = (int32_t *)(p + L.preds);
     return s;
 }
@@ -94,11 +98,34 @@ typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 __device__ __forceinline__ lds_u16 *lds16_ptr(uint32_t *p) { return (lds_u16 *)p; }
 
+// With 8-bit entries (four per word) a resident vertex's entry is relative
+// to base8, which follows the bands: e in [1, LDS8_WIN] is the distance
+// base8 + e - 1; 0 is a vertex settled below base8, whose distance is in d[];
+// LDS8_FAR is a distance that did not fit the window when it was set, kept in
+// d[]; LDS8_INF is unreached.  base8 only moves between bands, to a closed
+// band's threshold (every value offered later lies above it): entries below
+// the new base are written to d[] and become 0, the others are re-based.
+#define LDS8_INF 0xffu
+#define LDS8_FAR 0xfeu
+#define LDS8_WIN 253u
+#define LDS8_REBASE 64u // re-base once the band threshold is this far above base8
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+__device__ __forceinline__ lds_u8 *lds8_ptr(uint32_t *p) { return (lds_u8 *)p; }
+
 __device__ __forceinline__ uint32_t dist_get(const Slab &S, uint32_t u)
 {
     uint32_t r;
     if ((int32_t)u < S.H) {
-        if (S.w16) {
+        if (S.w8) {
+            const uint32_t e = lds8_ptr(S.ld)[u];
+            if (e - 1u < LDS8_WIN)
+                r = S.base8 + e - 1u;
+            else if (e == LDS8_INF)
+                r = BC_INF;
+            else
+                r = S.d[u]; // settled below the base, or kept in d[]
+        } else if (S.w16) {
             r = lds16_ptr(S.ld)[u];
             if (r == LDS16_INF)
                 r = BC_INF;
@@ -113,10 +140,41 @@ __device__ __forceinline__ uint32_t dist_get(const Slab &S, uint32_t u)
     return r;
 }
 
+// dist_get for the pre-check of a relaxation: a vertex settled below the
+// 8-bit base can take no offered value (each lies above the base), so 0
+// stands in for its distance there without a read of d[].
+__device__ __forceinline__ uint32_t dist_peek(const Slab &S, uint32_t u)
+{
+    if (S.w8 && (int32_t)u < S.H) {
+        const uint32_t e = lds8_ptr(S.ld)[u];
+        if (e - 1u < LDS8_WIN)
+            return S.base8 + e - 1u;
+        if (e == 0u)
+            return 0u;
+        return e == LDS8_INF ? BC_INF : S.d[u];
+    }
+    return dist_get(S, u);
+}
+
+// Single-thread store of a distance (no concurrent access to the entry's word).
 __device__ __forceinline__ void dist_set(const Slab &S, uint32_t u, uint32_t v)
 {
     if ((int32_t)u < S.H) {
-        if (S.w16) {
+        if (S.w8) {
+            uint32_t e;
+            if (v == BC_INF) {
+                e = LDS8_INF;
+            } else if (v < S.base8) {
+                e = 0u;
+                S.d[u] = v;
+            } else if (v - S.base8 + 1u <= LDS8_WIN) {
+                e = v - S.base8 + 1u;
+            } else {
+                e = LDS8_FAR;
+                S.d[u] = v;
+            }
+            lds8_ptr(S.ld)[u] = (uint8_t)e;
+        } else if (S.w16) {
             lds16_ptr(S.ld)[u] =
                 (uint16_t)(v < LDS16_FAR ? v : v == BC_INF ? LDS16_INF : LDS16_FAR);
             if (v >= LDS16_FAR)

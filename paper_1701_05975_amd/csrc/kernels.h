@@ -20,7 +20,7 @@ struct BatchArgs {
     const int32_t *iperm;         // caller id -> internal id (null: identity)
     const int32_t *perm;          // internal id -> caller id (null: identity)
     int32_t H;                    // distances of internal vertices 0..H-1 kept in LDS
-    int32_t lds16;                // LDS entries are 16-bit (65535 = kept in the slab)
+    int32_t lds_bits;             // width of the LDS distance entries: 32, 16 or 8 (8: packed arcs)
     int32_t hubs;                 // the graph has vertices of more than wg_deg arcs
     int32_t kahn;                 // 1: dependencies along the recorded DAG; 0: band pulls
     int32_t vw;                   // expansion: 0 adaptive lane/wave, else lanes per vertex
@@ -71,8 +71,10 @@ struct PlainArgs {
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st);
-int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, bool w16, size_t lds_bytes);
-int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, bool w16);
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, int lds_bits, size_t lds_bytes);
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, int lds_bits);
+// dynamic LDS of a batched launch: H resident distances of lds_bits each
+size_t batched_lds_bytes(int H, int lds_bits);
 hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nslabs, int n,
                                   double *out, const int32_t *perm, hipStream_t st);
 hipError_t launch_plain_source(const PlainArgs &a, bool packed, int grid, int32_t s,

@@ -275,7 +275,46 @@ __device__ __forceinline__ bool wg_band_rounds(const DevGraph &g, const Slab &S,
     }
 }
 
-template <bool PACKED, int NT, bool ATOMIC_BC, bool W16, bool BKT>
+// Re-bases the 8-bit LDS distances to nb (see LDS8_WIN): entries below nb are
+// settled, their distances go to d[] and they become 0; the others are
+// shifted (an entry kept in d[] comes back into the window when it fits).
+// No other access to the entries may run meanwhile.
+__device__ __forceinline__ void lds8_rebase(const Slab &S, uint32_t nb, int tid, int nthreads)
+{
+    const uint32_t ob = S.base8;
+    const int words = (S.H + 3) >> 2;
+    for (int wi = tid; wi < words; wi += nthreads) {
+        const uint32_t w = lds_ptr(S.ld)[wi];
+        uint32_t out = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t u = (uint32_t)wi * 4u + (uint32_t)j;
+            const uint32_t h = (w >> (8 * j)) & 0xffu;
+            uint32_t e = h;
+            if ((int32_t)u < S.H) {
+                if (h - 1u < LDS8_WIN) {
+                    const uint32_t dv = ob + h - 1u;
+                    if (dv < nb) {
+                        S.d[u] = dv;
+                        e = 0u;
+                    } else {
+                        e = dv - nb + 1u; // at most h, as nb >= ob
+                    }
+                } else if (h == LDS8_FAR) {
+                    const uint32_t dv = S.d[u];
+                    if (dv < nb)
+                        e = 0u;
+                    else if (dv - nb + 1u <= LDS8_WIN)
+                        e = dv - nb + 1u;
+                }
+            }
+            out |= e << (8 * j);
+        }
+        lds_ptr(S.ld)[wi] = out;
+    }
+}
+
+template <bool PACKED, int NT, bool ATOMIC_BC, int LB, bool BKT>
 __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 {
     __shared__ WgCtl C;
@@ -287,7 +326,9 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
     Slab S = slab_at(a.slab_base, a.L, blockIdx.x);
     S.ld = lds_dist;
     S.H = a.H;
-    S.w16 = W16; // a compile-time constant: each instantiation keeps one distance path
+    // compile-time constants: each instantiation keeps one distance path
+    S.w16 = LB == 16;
+    S.w8 = LB == 8;
     if (!ATOMIC_BC)
         for (int v = tid; v < n; v += NT)
             S.bcp[v] = 0.0;
@@ -334,9 +375,11 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.gen = 0;
         }
         // Initialisation (Alg. 1): d = inf and sigma = 0 everywhere.
-        if (S.w16) {
-            for (int v = tid; v < (S.H + 1) / 2; v += NT)
-                lds_ptr(S.ld)[v] = 0xffffffffu; // both entries LDS16_INF
+        S.base8 = 0;
+        if (LB < 32) {
+            constexpr int per = 32 / LB;
+            for (int v = tid; v < (S.H + per - 1) / per; v += NT)
+                lds_ptr(S.ld)[v] = 0xffffffffu; // every entry LDS16_INF / LDS8_INF
         } else {
             for (int v = tid; v < S.H; v += NT)
                 S.ld[v] = BC_INF;
@@ -357,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                     if (!ATOMIC_BC && v != ps)
                         S.bcp[v] += S.delta[v];
                 }
-                if (W16 || v >= S.H)
+                if (LB < 32 || v >= S.H)
                     S.d[v] = BC_INF;
                 S.sigma[v] = 0;
                 if (a.kahn)
@@ -461,7 +504,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                         for (uint32_t e = hb + tid; e < he; e += NT) {
                             uint32_t u, w;
                             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                            relax<WG_SCOPE, BKT>(S, ec, u, hd + w, dist_get(S, u), (uint32_t)v, fmin,
+                            relax<WG_SCOPE, BKT>(S, ec, u, hd + w, dist_peek(S, u), (uint32_t)v, fmin,
                                             omin, st_imp);
                         }
                     }
@@ -513,6 +556,16 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
                 C.band_start = b1;
             }
             __syncthreads();
+            if constexpr (LB == 8) {
+                // every vertex below the closed band's threshold is settled and
+                // every later offered value lies above it
+                if (C.thr - S.base8 > LDS8_REBASE) {
+                    const uint32_t nb = C.thr;
+                    lds8_rebase(S, nb, tid, NT);
+                    __syncthreads();
+                    S.base8 = nb;
+                }
+            }
             if constexpr (BKT) {
                 const bool more = bucket_next_band<NT>(S, C, a, iter_cap);
                 phase_mark(C, tmark, 4);
@@ -671,7 +724,13 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
         phase_mark(C, tmark, 3);
         // The LDS-resident distances go back to the slab so that the slab
         // holds the complete per-source state.
-        if (S.w16) {
+        if (S.w8) {
+            for (int v = tid; v < S.H; v += NT) {
+                const uint32_t e = lds8_ptr(S.ld)[v];
+                if (e - 1u < LDS8_WIN)
+                    S.d[v] = S.base8 + e - 1u; // else d[v] already holds it (or BC_INF)
+            }
+        } else if (S.w16) {
             for (int v = tid; v < S.H; v += NT) {
                 const uint32_t x = lds16_ptr(S.ld)[v];
                 if (x < LDS16_FAR)
@@ -1188,47 +1247,60 @@ __global__ void k_dynamic_apply(double *bc, const double *before, const double *
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <bool PACKED, int NT, bool ATOMIC, bool W16, bool BKT>
+size_t batched_lds_bytes(int H, int lb)
+{
+    const int per = 32 / lb;
+    return (size_t)((H + per - 1) / per) * 4;
+}
+
+template <bool PACKED, int NT, bool ATOMIC, int LB, bool BKT>
 static void launch_batched_t(const BatchArgs &a, int nslabs, hipStream_t st)
 {
-    const size_t lds = W16 ? (size_t)((a.H + 1) / 2) * 4 : (size_t)a.H * sizeof(uint32_t);
+    const size_t lds = batched_lds_bytes(a.H, LB);
     if (lds > 48 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC, W16, BKT>,
+        (void)hipFuncSetAttribute((const void *)k_batched<PACKED, NT, ATOMIC, LB, BKT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC, W16, BKT>), dim3(nslabs), dim3(NT), lds, st,
+    hipLaunchKernelGGL((k_batched<PACKED, NT, ATOMIC, LB, BKT>), dim3(nslabs), dim3(NT), lds, st,
                        a);
 }
 
 // Every instantiation of the batched kernel: (packed arcs, threads, atomic
-// output, 16-bit LDS distances, far-bucket ring).  The ring is built for
-// packed-arc graphs only; the others keep the two-tier far pile.
+// output, LDS distance width, far-bucket ring).  The ring and the 8-bit
+// distances are built for packed-arc graphs only; the others keep the
+// two-tier far pile and 16- or 32-bit distances.
 #define BC_FOR_EACH_BATCHED(X)                                                                  \
-    X(true, 256, false, false, false) X(true, 256, true, false, false)                         \
-    X(true, 512, false, false, false) X(true, 512, true, false, false)                         \
-    X(true, 1024, false, false, false) X(true, 1024, true, false, false)                       \
-    X(false, 256, false, false, false) X(false, 256, true, false, false)                       \
-    X(false, 512, false, false, false) X(false, 512, true, false, false)                       \
-    X(false, 1024, false, false, false) X(false, 1024, true, false, false)                     \
-    X(true, 256, false, true, false) X(true, 256, true, true, false)                           \
-    X(true, 512, false, true, false) X(true, 512, true, true, false)                           \
-    X(true, 1024, false, true, false) X(true, 1024, true, true, false)                         \
-    X(false, 256, false, true, false) X(false, 256, true, true, false)                         \
-    X(false, 512, false, true, false) X(false, 512, true, true, false)                         \
-    X(false, 1024, false, true, false) X(false, 1024, true, true, false)                       \
-    X(true, 256, false, false, true) X(true, 256, true, false, true)                           \
-    X(true, 256, false, true, true) X(true, 256, true, true, true)                             \
-    X(true, 512, false, false, true) X(true, 512, true, false, true)                           \
-    X(true, 512, false, true, true) X(true, 512, true, true, true)                             \
-    X(true, 1024, false, false, true) X(true, 1024, true, false, true)                         \
-    X(true, 1024, false, true, true) X(true, 1024, true, true, true)
+    X(true, 256, false, 32, false) X(true, 256, true, 32, false)                               \
+    X(true, 512, false, 32, false) X(true, 512, true, 32, false)                               \
+    X(true, 1024, false, 32, false) X(true, 1024, true, 32, false)                             \
+    X(false, 256, false, 32, false) X(false, 256, true, 32, false)                             \
+    X(false, 512, false, 32, false) X(false, 512, true, 32, false)                             \
+    X(false, 1024, false, 32, false) X(false, 1024, true, 32, false)                           \
+    X(true, 256, false, 16, false) X(true, 256, true, 16, false)                               \
+    X(true, 512, false, 16, false) X(true, 512, true, 16, false)                               \
+    X(true, 1024, false, 16, false) X(true, 1024, true, 16, false)                             \
+    X(false, 256, false, 16, false) X(false, 256, true, 16, false)                             \
+    X(false, 512, false, 16, false) X(false, 512, true, 16, false)                             \
+    X(false, 1024, false, 16, false) X(false, 1024, true, 16, false)                           \
+    X(true, 256, false, 8, false) X(true, 256, true, 8, false)                                 \
+    X(true, 512, false, 8, false) X(true, 512, true, 8, false)                                 \
+    X(true, 1024, false, 8, false) X(true, 1024, true, 8, false)                               \
+    X(true, 256, false, 32, true) X(true, 256, true, 32, true)                                 \
+    X(true, 256, false, 16, true) X(true, 256, true, 16, true)                                 \
+    X(true, 256, false, 8, true) X(true, 256, true, 8, true)                                   \
+    X(true, 512, false, 32, true) X(true, 512, true, 32, true)                                 \
+    X(true, 512, false, 16, true) X(true, 512, true, 16, true)                                 \
+    X(true, 512, false, 8, true) X(true, 512, true, 8, true)                                   \
+    X(true, 1024, false, 32, true) X(true, 1024, true, 32, true)                               \
+    X(true, 1024, false, 16, true) X(true, 1024, true, 16, true)                               \
+    X(true, 1024, false, 8, true) X(true, 1024, true, 8, true)
 
 hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_bc, int nslabs,
                           hipStream_t st)
 {
-    const bool w16 = a.lds16 != 0;
+    const int lb = a.lds_bits;
     const bool bkt = a.buckets != 0;
 #define BC_CASE(P, T, A, W, B)                                                                  \
-    if (packed == P && nt == T && atomic_bc == A && w16 == W && bkt == B) {                     \
+    if (packed == P && nt == T && atomic_bc == A && lb == W && bkt == B) {                      \
         launch_batched_t<P, T, A, W, B>(a, nslabs, st);                                         \
         return hipGetLastError();                                                               \
     }
@@ -1237,17 +1309,17 @@ hipError_t launch_batched(const BatchArgs &a, bool packed, int nt, bool atomic_b
     return hipErrorInvalidValue;
 }
 
-int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, bool w16)
+int batched_blocks_per_cu(bool packed, int nt, bool atomic_bc, int lb)
 {
-    return batched_blocks_per_cu_lds(packed, nt, atomic_bc, w16, 0);
+    return batched_blocks_per_cu_lds(packed, nt, atomic_bc, lb, 0);
 }
 
-int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, bool w16, size_t lds_bytes)
+int batched_blocks_per_cu_lds(bool packed, int nt, bool atomic_bc, int lb, size_t lds_bytes)
 {
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
 #define BC_OCC(P, T, A, W, B)                                                                   \
-    if (packed == P && nt == T && atomic_bc == A && w16 == W && !B) {                           \
+    if (packed == P && nt == T && atomic_bc == A && lb == W && !B) {                            \
         if (lds_bytes > 48 * 1024)                                                              \
             (void)hipFuncSetAttribute((const void *)k_batched<P, T, A, W, B>,                   \
                                       hipFuncAttributeMaxDynamicSharedMemorySize,               \

@@ -25,6 +25,38 @@ template <int SCOPE>
 __device__ __forceinline__ uint32_t dist_min(const Slab &S, uint32_t u, uint32_t v)
 {
     if ((int32_t)u < S.H) {
+        if (S.w8) {
+            // 8-bit entry (see LDS8_WIN): compare-and-swap its word.  v lies
+            // above the base (it is offered from the band being expanded), so
+            // an entry of 0 (settled below the base) is already smaller.
+            // Entries only move down (unreached, then kept in d[] or a value
+            // in the window, then smaller values), so the loop ends.
+            lds_u32 *wp = lds_ptr(S.ld) + (u >> 2);
+            const uint32_t sh = (u & 3u) * 8u;
+            const uint32_t fit = v - S.base8 + 1u; // window code of v, if at most LDS8_WIN
+            uint32_t cur = *wp;
+            for (;;) {
+                const uint32_t h = (cur >> sh) & 0xffu;
+                if (h - 1u < LDS8_WIN && S.base8 + h - 1u <= v)
+                    return S.base8 + h - 1u; // already at most v
+                if (h == 0u)
+                    return 0u;
+                if (fit > LDS8_WIN && h == LDS8_FAR) // kept in d[]
+                    return atomic_min_u32<SCOPE>(&S.d[u], v);
+                // h is unreached, kept in d[] while v fits, or a larger value
+                const uint32_t e = fit <= LDS8_WIN ? fit : LDS8_FAR;
+                const uint32_t nw = (cur & ~(0xffu << sh)) | (e << sh);
+                uint32_t expect = cur;
+                if (__hip_atomic_compare_exchange_strong(wp, &expect, nw, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    if (e == LDS8_FAR) // first value that does not fit (h was unreached)
+                        return atomic_min_u32<SCOPE>(&S.d[u], v);
+                    return h - 1u < LDS8_WIN ? S.base8 + h - 1u : BC_INF; // d[u] was larger
+                }
+                cur = expect;
+            }
+        }
         if (!S.w16)
             return __hip_atomic_fetch_min(lds_ptr(S.ld) + u, v, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -314,7 +346,7 @@ __device__ __forceinline__ void expand_pass_vw(const DevGraph &g, const Slab &S,
         for (uint32_t e = beg + sub; e < end; e += W) {
             uint32_t u, w;
             arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-            relax<SCOPE, BKT>(S, c, u, dv + w, dist_get(S, u), (uint32_t)v, far_min, outer_min, nimp);
+            relax<SCOPE, BKT>(S, c, u, dv + w, dist_peek(S, u), (uint32_t)v, far_min, outer_min, nimp);
         }
     }
 }
@@ -368,7 +400,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
                 }
 #pragma unroll
                 for (int j = 0; j < LANE_UNROLL; ++j)
-                    du[j] = e0 + j < end ? dist_get(S, u[j]) : 0u;
+                    du[j] = e0 + j < end ? dist_peek(S, u[j]) : 0u;
 #pragma unroll
                 for (int j = 0; j < LANE_UNROLL; ++j)
                     if (e0 + j < end)
@@ -406,7 +438,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
                 }
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    du[j] = e0 + G * j < me ? dist_get(S, u[j]) : 0u;
+                    du[j] = e0 + G * j < me ? dist_peek(S, u[j]) : 0u;
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     if (e0 + G * j < me)
@@ -424,7 +456,7 @@ __device__ __forceinline__ void expand_pass(const DevGraph &g, const Slab &S, co
             for (uint32_t e = hb + lane; e < he; e += WAVE) {
                 uint32_t u, w;
                 arc_at<PACKED>(g.arc, g.wt, e, g.wshift, g.wmask, u, w);
-                relax<SCOPE, BKT>(S, c, u, hd + w, dist_get(S, u), hv, far_min, outer_min, nimp);
+                relax<SCOPE, BKT>(S, c, u, hd + w, dist_peek(S, u), hv, far_min, outer_min, nimp);
             }
         }
     }

@@ -50,7 +50,7 @@ struct SweepCtx {
     int cap = 0;
     int slots = 0;
     int lds_vertices = 0;
-    int lds16 = 0;
+    int lds_bits = 32;
     std::vector<bcserve::SweepItem> items;
     ~SweepCtx()
     {
@@ -194,7 +194,7 @@ class HipExec {
         a.iperm = g->iperm_dev();
         a.perm = g->perm_dev();
         a.H = c->lds_vertices;
-        a.lds16 = c->lds16;
+        a.lds_bits = c->lds_bits;
         set_tier_args(g, tier_for(g, 0), tier_for(g, 1), tier_for(g, 2), a);
         a.kahn = dep_mode_for(g) == 1 ? 1 : 0;
         a.ebc = nullptr;
@@ -398,7 +398,7 @@ class HipExec {
             c->slots = slots;
             c->cap = cap;
             c->lds_vertices = H;
-            c->lds16 = bits == 16;
+            c->lds_bits = bits;
             hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
             hip_check(hipEventCreateWithFlags(&c->done, hipEventDisableTiming), "event");
             c->ws.L = L;

@@ -3,7 +3,9 @@
 The library's autotuner picked these on MI355X (``python bench.py --autotune``
 prints its choice); they are pinned so that the benchmark, its rocprofv3
 profiles and the full-size parity tests launch identical kernels.  The grid
-workload is configured with 256 sources in flight per launch.
+workload is configured with 256 sources in flight per launch.  R-MAT also
+takes 8-bit LDS distances (measured against 16-bit on one box; the autotuner
+does not search the entry width).
 """
 
 LAUNCH = {
@@ -11,7 +13,7 @@ LAUNCH = {
     "er1000": dict(delta=400, wg_threads=256, lane_max_deg=16),
     "grid1000": dict(delta=182, wg_threads=1024, lane_max_deg=128, batch=256),
     "rmat22": dict(delta=2, wg_threads=1024, lane_max_deg=8, expand_lane_deg=16,
-                   wave_max_deg=64, wg_min_deg=4096),
+                   wave_max_deg=64, wg_min_deg=4096, lds_bits=8),
 }
 
 # Serving run over the eight resident graphs: the Poisson arrival rate is

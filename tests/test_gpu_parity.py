@@ -45,6 +45,11 @@ OPTION_SETS = [
     dict(lds_bits=16),
     dict(lds_bits=32),
     dict(lds_bits=16, lds_vertices=5, wg_threads=512),
+    dict(lds_bits=8),
+    dict(lds_bits=8, lds_vertices=5, wg_threads=512),
+    dict(lds_bits=8, delta=1, far_buckets=1),
+    dict(lds_bits=8, delta=1 << 28),
+    dict(lds_bits=8, delta=3, far_buckets=1, accumulate=2, wg_threads=256),
     dict(far_buckets=1),
     dict(far_buckets=1, delta=1, wg_threads=256),
     dict(far_buckets=1, delta=2, lds_vertices=-1, accumulate=2),
@@ -255,7 +260,7 @@ def test_empty_and_degenerate_inputs():
     with pytest.raises(bc.BCError) as ei:
         G.bc(np.array([1], np.int32))
     assert ei.value.status == bc.BC_E_INVAL
-    for bad in (dict(lds_bits=8), dict(virtual_warp=3), dict(node_parallel=2)):
+    for bad in (dict(lds_bits=12), dict(virtual_warp=3), dict(node_parallel=2)):
         with pytest.raises(bc.BCError) as ei:
             G.bc(None, **bad)
         assert ei.value.status == bc.BC_E_INVAL, bad
@@ -411,6 +416,28 @@ def test_vertices_without_inarcs(hint):
         for s in (0, 299, 300, 450, g.n - 1):
             check_state(g, G, s)
         G.close()
+
+
+@pytest.mark.parametrize("directed", [True, False])
+def test_lds_8bit_window(directed):
+    # 8-bit LDS distances relative to a window that follows the bands: every
+    # vertex resident, weights far beyond the window's width (values kept in
+    # device memory, brought back in at a re-base) and narrow bands (many
+    # re-bases), several sources per slab; distances, counts and dependencies
+    # exact at every vertex
+    g = gg.random_graph(3000, 0.003, 1, 600, seed=41, directed=directed)
+    G = bc.Graph(g)
+    want = oracle.oracle_bc(g, np.arange(g.n))
+    srcs = np.random.default_rng(3).permutation(g.n).astype(np.int32)
+    for opts in (dict(delta=1), dict(delta=5, far_buckets=1), dict(delta=64, batch=2),
+                 dict(delta=300, far_buckets=1, batch=3)):
+        got, st = G.bc(srcs, lds_bits=8, lds_vertices=g.n, **opts)
+        assert st["lds_bits"] == 8 and st["lds_vertices"] == g.n, st
+        rel_close(got, want, 1e-9)
+    for s in (0, 1234, g.n - 1):
+        check_state(g, G, s, lds_bits=8, lds_vertices=g.n, delta=2)
+        check_state(g, G, s, lds_bits=8, lds_vertices=g.n, delta=7, far_buckets=1)
+    G.close()
 
 
 def test_device_entry_point_with_torch_tensors():
