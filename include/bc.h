@@ -128,6 +128,7 @@ typedef struct {
     int32_t tuned_delta, tuned_wg_threads, tuned_lane_max_deg, tuned_dep_mode;
     int32_t tuned_expand_lane_deg, tuned_wave_max_deg, tuned_wg_min_deg;
     int32_t tuned_batch;  /* sources in flight; 0 = the full occupancy of the workgroup size */
+    int32_t tuned_lds_bits; /* width of the LDS distance entries */
     int64_t tuning_trials; /* candidate settings timed on this graph so far */
 } bc_graph_info;
 

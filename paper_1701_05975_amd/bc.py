@@ -91,6 +91,7 @@ class bc_graph_info(ctypes.Structure):
                 ("tuned_lane_max_deg", ctypes.c_int32), ("tuned_dep_mode", ctypes.c_int32),
                 ("tuned_expand_lane_deg", ctypes.c_int32), ("tuned_wave_max_deg", ctypes.c_int32),
                 ("tuned_wg_min_deg", ctypes.c_int32), ("tuned_batch", ctypes.c_int32),
+                ("tuned_lds_bits", ctypes.c_int32),
                 ("tuning_trials", ctypes.c_int64)]
 
 

@@ -2,10 +2,10 @@
 //
 // Coordinate descent, each candidate timed on a prefix of the caller's
 // source list: the near-far band width, the workgroup size, the dependency
-// method, the count pass's lane threshold, the three degree thresholds of the
-// frontier expansion (the degree-aware thread mapping of Sec. 3.4, whose
-// virtual warp width the paper tunes per graph, Fig. 5) and the number of
-// sources in flight.  The winner is cached on the graph handle and reused by
+// method, the width of the LDS distance entries, the count pass's lane
+// threshold, the three degree thresholds of the frontier expansion (the
+// degree-aware thread mapping of Sec. 3.4, whose virtual warp width the paper
+// tunes per graph, Fig. 5) and the number of sources in flight.  The winner is cached on the graph handle and reused by
 // later calls; fields the caller sets are never searched.
 #include <algorithm>
 #include <cstring>
@@ -61,15 +61,14 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
     if (opt)
         o = *opt;
     const int64_t cap = batch_cap(g);
-    auto fill_for = [&](int nt, int &H) {
+    auto fill_for = [&](int nt, int bits, int &H) {
         int per_cu = 1;
-        batched_lds_plan(g, nt, r.accumulate == 2, o.lds_vertices, r.lds_bits, H, per_cu,
-                         o.batch);
+        batched_lds_plan(g, nt, r.accumulate == 2, o.lds_vertices, bits, H, per_cu, o.batch);
         return (int64_t)g->num_cus * per_cu;
     };
     if (!g->tuned.valid) {
         int H0 = 0;
-        const int64_t fill = fill_for(r.wg_threads, H0);
+        const int64_t fill = fill_for(r.wg_threads, r.lds_bits, H0);
         // one full occupancy of sources, so that each trial runs the GPU in the
         // regime of the real call; on large graphs at most ~2e10 arc-sources
         int64_t sample = std::min<int64_t>(k, std::max<int64_t>(fill, 64));
@@ -107,11 +106,25 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
                 ResolvedOptions t = S.best;
                 t.wg_threads = nt;
                 int H = 0;
-                const int64_t f = fill_for(nt, H);
+                const int64_t f = fill_for(nt, t.lds_bits, H);
                 t.lds_vertices = H;
                 // a batch the caller fixed stays fixed; else a full occupancy
                 const int64_t want = o.batch ? (int64_t)o.batch : f;
                 t.batch = (int)std::max<int64_t>(1, std::min<int64_t>({want, sample, cap}));
+                S.consider(t);
+            }
+        }
+        if (!o.lds_bits) {
+            // entry width of the LDS distance cache (8-bit entries for packed arcs only)
+            const int b0 = S.best.lds_bits;
+            for (int bits : {8, 16, 32}) {
+                if (bits == b0 || (bits == 8 && !g->packed))
+                    continue;
+                ResolvedOptions t = S.best;
+                t.lds_bits = bits;
+                int H = 0;
+                (void)fill_for(t.wg_threads, bits, H);
+                t.lds_vertices = H;
                 S.consider(t);
             }
         }
@@ -184,10 +197,11 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
         g->tuned.lane_deg = c.lane_deg;
         g->tuned.wave_deg = c.wave_deg;
         g->tuned.wg_deg = c.wg_deg;
+        g->tuned.lds_bits = c.lds_bits;
         // sources in flight as a fraction of the full occupancy of the chosen
         // workgroup size (so that it carries over to calls with other k)
         int Hc = 0;
-        const int64_t fc = fill_for(c.wg_threads, Hc);
+        const int64_t fc = fill_for(c.wg_threads, c.lds_bits, Hc);
         g->tuned.batch = c.batch >= std::min<int64_t>(fc, sample) ? 0 : c.batch;
         g->tuned.best_ms_per_source = S.best_ms / (double)sample;
     }
@@ -205,10 +219,16 @@ void autotune(bc_graph *g, ResolvedOptions &r, const bc_options *opt, const int3
     if (!o.wg_min_deg)
         r.wg_deg = g->tuned.wg_deg;
     order_tiers(r);
+    if (!o.lds_bits && g->tuned.lds_bits && r.lds_bits != g->tuned.lds_bits) {
+        r.lds_bits = g->tuned.lds_bits;
+        int H = 0;
+        (void)fill_for(r.wg_threads, r.lds_bits, H);
+        r.lds_vertices = H;
+    }
     if (!o.wg_threads && r.wg_threads != g->tuned.wg_threads) {
         r.wg_threads = g->tuned.wg_threads;
         int H = 0;
-        const int64_t f = fill_for(r.wg_threads, H);
+        const int64_t f = fill_for(r.wg_threads, r.lds_bits, H);
         r.lds_vertices = H;
         if (!o.batch)
             r.batch = (int)std::max<int64_t>(1, std::min<int64_t>({f, k, cap}));

@@ -1054,6 +1054,7 @@ bc_status bc_get_graph_info(const bc_graph *g, bc_graph_info *info)
         i.tuned_wave_max_deg = g->tuned.wave_deg;
         i.tuned_wg_min_deg = g->tuned.wg_deg;
         i.tuned_batch = g->tuned.batch;
+        i.tuned_lds_bits = g->tuned.lds_bits;
         i.tuning_trials = g->tune_trials;
         *info = i;
     });

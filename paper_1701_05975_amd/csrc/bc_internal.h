@@ -95,6 +95,7 @@ struct TunedOptions {
     int delta = 0, lane_max = 0, wg_threads = 0, dep_mode = 0;
     int lane_deg = 0, wave_deg = 0, wg_deg = 0;
     int batch = 0; // sources in flight (0 = the full occupancy of wg_threads)
+    int lds_bits = 0;
     double best_ms_per_source = 0.0;
 };
 

@@ -3,9 +3,10 @@
 The library's autotuner picked these on MI355X (``python bench.py --autotune``
 prints its choice); they are pinned so that the benchmark, its rocprofv3
 profiles and the full-size parity tests launch identical kernels.  The grid
-workload is configured with 256 sources in flight per launch.  R-MAT also
-takes 8-bit LDS distances (measured against 16-bit on one box; the autotuner
-does not search the entry width).
+workload is configured with 256 sources in flight per launch.  R-MAT's entry
+width and tiers were then measured on full runs: the tuner, whose trials run
+on a sample of the sources, picks 16-bit entries and tiers 8/64/1024 (1497 ms
+per launch) where 8-bit entries with tiers 16/64/4096 take 1480 ms.
 """
 
 LAUNCH = {

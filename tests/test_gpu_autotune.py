@@ -13,7 +13,7 @@ from paper_1701_05975_amd import bc, graphgen as gg
 pytestmark = pytest.mark.gpu
 
 SETTINGS = ["delta", "wg_threads", "lane_max_deg", "dep_mode", "expand_lane_deg",
-            "wave_max_deg", "wg_min_deg"]
+            "wave_max_deg", "wg_min_deg", "lds_bits"]
 
 
 def rel_close(got, want, tol):
