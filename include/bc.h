@@ -220,7 +220,9 @@ typedef struct {
                              rest), rescanned at every band change.  0 = the ring when the
                              maximum weight spans at least 16 band widths, else the pile.
                              The ring needs head and weight packed in one arc word
-                             (bc_graph_info.packed_arcs); other graphs keep the pile */
+                             (bc_graph_info.packed_arcs), fewer than 2^30 vertices and
+                             fewer than 2^30 bands up to (n - 1) times the maximum
+                             weight; other graphs keep the pile */
     void *stream;         /* hipStream_t to run on; NULL = the graph's own stream */
 } bc_options;
 

@@ -744,7 +744,12 @@ void bucket_plan(const bc_graph *g, const ResolvedOptions &r, int &buckets, int 
     // weights span many bands, where the pile would be rescanned many times.
     const int64_t spans = ((int64_t)g->wmax + r.delta - 1) / std::max(r.delta, 1);
     nbk = (int)std::min<int64_t>(spans + 2, BC_BUCKETS_MAX);
-    buckets = g->packed && (r.far_buckets == 1 || (r.far_buckets == 0 && spans >= 16));
+    // bucket keys (BUCKET_KEY) stay below the count pass's predecessor
+    // encodings only while vertex ids and bucket indices stay below 2^30
+    const int64_t last_bucket = (int64_t)std::max(g->n - 1, 0) * g->wmax / std::max(r.delta, 1);
+    const bool keys_fit = g->n < (1 << 30) && last_bucket < (int64_t)1 << 30;
+    buckets = g->packed && keys_fit &&
+              (r.far_buckets == 1 || (r.far_buckets == 0 && spans >= 16));
 }
 
 void set_tier_args(const bc_graph *g, int lane_deg, int wave_deg, int wg_deg, BatchArgs &a)

@@ -72,8 +72,8 @@ __device__ __forceinline__ void phase_mark(WgCtl &C, long long &t0, int phase)
 // scanned: entries of the new band's bucket join the band at once, entries of
 // later buckets in the window move into the ring (or stay, if theirs is
 // full), settled entries are dropped.  Then the ring bucket's entries move into
-// the near queue as the band [b delta, (b + 1) delta); entries whose distance
-// dropped below their bucket since (settled in an earlier band) and repeats
+// the near queue as the band [b delta, (b + 1) delta); entries whose vertex
+// was put in a lower bucket since, or settled in an earlier band, and repeats
 // are skipped.  Returns false once no vertex is left, or when the band bound
 // trips.
 template <int NT>
@@ -158,6 +158,10 @@ __device__ __forceinline__ bool bucket_next_band(const Slab &S, WgCtl &C, const 
                         const int k = atomicAdd(&C.bcnt[slot], 1);
                         if (k < a.bcap) {
                             S.fa[(size_t)slot * (size_t)a.bcap + (size_t)k] = v;
+                            // the entry is current for bucket b (its key at most b's
+                            // already when the pile took it from a full bucket)
+                            __hip_atomic_fetch_min(&S.pred1[v], BUCKET_KEY(b), __ATOMIC_RELAXED,
+                                                   WG_SCOPE);
                             keep = false;
                         } else {
                             C.forced = 1;
@@ -201,7 +205,10 @@ __device__ __forceinline__ bool bucket_next_band(const Slab &S, WgCtl &C, const 
         int32_t v = 0;
         if (i < len) {
             v = in[i];
-            if (dist_get(S, v) / D == bcur)
+            // current exactly when the vertex's least bucket is still this one:
+            // a later push to a lower bucket lowers the key, and the count pass
+            // of the band a vertex settles in overwrites it (no distance read)
+            if (S.pred1[v] == BUCKET_KEY(bcur))
                 mv = atomic_xchg_i32<WG_SCOPE>(&S.stamp[v], C.gen) != C.gen;
         }
         int k = wave_alloc(&C.near_len, mv);

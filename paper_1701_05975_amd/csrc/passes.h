@@ -276,9 +276,10 @@ __device__ __forceinline__ void relax(const Slab &S, const ExpandCtx &c, uint32_
             pm = ot < c.band_gen;
         } else if (nd < c.bound) {
             if (BKT) {
-                const int32_t b = (int32_t)(nd / c.bdelta);
-                if (b < __hip_atomic_fetch_min(&S.pred1[u], b, __ATOMIC_RELAXED, SCOPE))
-                    bslot = b % c.nbk;
+                const uint32_t b = nd / c.bdelta;
+                if (BUCKET_KEY(b) <
+                    __hip_atomic_fetch_min(&S.pred1[u], BUCKET_KEY(b), __ATOMIC_RELAXED, SCOPE))
+                    bslot = (int)(b % (uint32_t)c.nbk);
             } else {
                 far_min = nd < far_min ? nd : far_min;
                 pf = (atomic_or_i32<SCOPE>(&S.infar[u], 1) & 1) == 0;
@@ -731,6 +732,8 @@ __device__ __forceinline__ bool keyed_count(const DevGraph &g, const Slab &S, co
             S.pred1[v] = -1;
             S.infar[v] = fl | VFLAG_TLIST;
         }
+    } else {
+        S.pred1[v] = -1; // a counted vertex's far-bucket value is gone (see VREC_PRED1)
     }
     return true;
 }
@@ -765,11 +768,9 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
         if (is_src) {
             // sigma[s] = 1 was set at initialisation; s has no DAG predecessors
             store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
-            if (RECORD) {
-                S.pred1[v] = -1;
-                if (end > beg)
-                    S.preds[beg] = -1;
-            }
+            S.pred1[v] = -1;
+            if (RECORD && end > beg)
+                S.preds[beg] = -1;
         }
         const uint32_t deg = end - beg;
         const bool heavy = valid && !is_src && !keyed && deg > c.wave_deg;
@@ -816,8 +817,8 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_u64<SCOPE>(&S.sigma[v], acc);
                 store_f64<SCOPE>(&S.delta[v], RECORD ? 0.0 : -1.0);
                 dag += tight;
+                S.pred1[v] = -1;
                 if (RECORD) {
-                    S.pred1[v] = -1;
                     if (beg + tight < end)
                         S.preds[beg + tight] = -1;
                     for (uint32_t j = 0; j < tight; ++j)
@@ -897,11 +898,9 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_u64<SCOPE>(&S.sigma[mv], acc);
                 store_f64<SCOPE>(&S.delta[mv], RECORD ? 0.0 : -1.0);
                 dag += rec;
-                if (RECORD) {
-                    S.pred1[mv] = -1;
-                    if (mb + rec < me)
-                        S.preds[mb + rec] = -1;
-                }
+                S.pred1[mv] = -1;
+                if (RECORD && mb + rec < me)
+                    S.preds[mb + rec] = -1;
             }
             if (RECORD && have && gready)
                 for (uint32_t j = sub; j < rec; j += EXPAND_GROUP)
@@ -961,11 +960,9 @@ __device__ __forceinline__ void sigma_round(const DevGraph &g, const Slab &S, co
                 store_u64<SCOPE>(&S.sigma[hv], acc);
                 store_f64<SCOPE>(&S.delta[hv], RECORD ? 0.0 : -1.0);
                 dag += tight;
-                if (RECORD) {
-                    S.pred1[hv] = -1;
-                    if (hb + tight < he)
-                        S.preds[hb + tight] = -1;
-                }
+                S.pred1[hv] = -1;
+                if (RECORD && hb + tight < he)
+                    S.preds[hb + tight] = -1;
             }
             if (RECORD && all_ready)
                 for (uint32_t j = lane; j < tight; j += WAVE)

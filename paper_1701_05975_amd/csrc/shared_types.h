@@ -54,7 +54,12 @@ struct DevGraph {
 #define VREC_INFAR 4  // i32 bit 0: in the inner far pile; bit 1: in the outer far pile
 #define VREC_SCNT 8   // i32 shortest-path-DAG successors not yet accumulated
 #define VREC_PRED1 12 // i32 the only DAG predecessor, or -1: the list in preds[]; before the
-                      // vertex is counted, the least far bucket it was put in (bucket ring)
+                      // vertex is counted (bucket ring), BUCKET_KEY of the least far bucket
+                      // it was put in: below every value the count pass writes, so a ring
+                      // entry is current exactly when its bucket's key is there
+// Ring bucket b as kept in the record: below every predecessor encoding while
+// buckets and vertex ids stay below 2^30 (the ring is only planned then).
+#define BUCKET_KEY(b) ((int32_t)((uint32_t)INT32_MIN + (uint32_t)(b)))
 #define VREC_SIGMA 16 // u64 shortest-path count (0 = not yet final in the count pass)
 #define VREC_DELTA 24 // f64 dependency (negative = not yet final in the pull pass)
 
