@@ -445,6 +445,8 @@ def main():
     ap.add_argument("--accumulate", type=int, default=0)
     ap.add_argument("--dep-mode", type=int, default=0)
     ap.add_argument("--lds-bits", type=int, default=0, help="LDS distance entry width (8, 16, 32)")
+    ap.add_argument("--lds-vertices", type=int, default=0,
+                    help="LDS-resident distances (-1: none; 0: as many as fit)")
     ap.add_argument("--far-buckets", type=int, default=0,
                     help="far values: 0 auto, 1 bucket ring, 2 two-tier pile")
     ap.add_argument("--edges", action="store_true",
@@ -518,6 +520,7 @@ def main():
                     lane_max_deg=args.lane_max or pinned.get("lane_max_deg", 0),
                     dep_mode=args.dep_mode or pinned.get("dep_mode", 0),
                     lds_bits=args.lds_bits or pinned.get("lds_bits", 0),
+                    lds_vertices=args.lds_vertices or pinned.get("lds_vertices", 0),
                     batch=args.batch or pinned.get("batch", 0), accumulate=args.accumulate,
                     far_buckets=args.far_buckets or pinned.get("far_buckets", 0),
                     expand_lane_deg=pinned.get("expand_lane_deg", 0),
