@@ -440,6 +440,25 @@ def test_lds_8bit_window(directed):
     G.close()
 
 
+def test_ring_key_range():
+    # the far-bucket ring keeps its least bucket as a key below every predecessor
+    # encoding, which needs bucket indices below 2^30: with weights up to 32767
+    # on 65536 vertices, band width 1 would allow ~2^31 buckets (the pile runs
+    # instead) while band width 4 keeps them below 2^30 (the ring runs)
+    g = gg.random_graph(65536, 0.00006, 1, 32767, seed=51, directed=True)
+    assert int(g.w.max()) > 30000
+    G = bc.Graph(g)
+    assert G.info()["packed_arcs"] == 1
+    srcs = gg.sample_sources(g, 24, seed=52)
+    want = oracle.oracle_bc(g, srcs)
+    for delta, ring in ((1, False), (4, True)):
+        got, st = G.bc(srcs, far_buckets=1, delta=delta)
+        assert st["far_buckets"] == (1 if ring else 2), (delta, st["far_buckets"])
+        rel_close(got, want, 1e-9)
+    check_state(g, G, int(srcs[0]), far_buckets=1, delta=4)
+    G.close()
+
+
 def test_device_entry_point_with_torch_tensors():
     torch = pytest.importorskip("torch")
     g = gg.ba_graph(3000, 3, 1, 50, seed=5)
