@@ -9,6 +9,8 @@
 // kernel advances a phase machine held in device memory and a grid-wide step
 // kernel executes the current phase, so the host only launches pairs of
 // kernels and polls for completion now and then.
+#include <algorithm>
+
 #include "kernels.h"
 #include "dev_common.h"
 #include "passes.h"
@@ -806,14 +808,24 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a)
 }
 
 // Sum of the per-slab partial centralities, slab after slab.
+// Sums the slabs' partial centralities into out.  Blocks along y take slab
+// groups of per_group slabs each (so that a small graph with many slabs still
+// fills the GPU); with more than one group they add into out, which the
+// launcher has zeroed, else each vertex's sum is stored.
 __global__ void k_reduce_partials(char *slab_base, SlabLayout L, int nslabs, int n, double *out,
-                                  const int32_t *perm)
+                                  const int32_t *perm, int per_group)
 {
+    const int b0 = (int)blockIdx.y * per_group;
+    const int b1 = b0 + per_group < nslabs ? b0 + per_group : nslabs;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         double acc = 0.0;
-        for (int b = 0; b < nslabs; ++b)
+        for (int b = b0; b < b1; ++b)
             acc += ((const double *)(slab_base + (size_t)b * L.stride + L.bcp))[v];
-        out[perm ? perm[v] : v] = acc;
+        const int o = perm ? perm[v] : v;
+        if (gridDim.y == 1)
+            out[o] = acc;
+        else
+            unsafeAtomicAdd(&out[o], acc);
     }
 }
 
@@ -1351,8 +1363,19 @@ hipError_t launch_reduce_partials(char *slab_base, const SlabLayout &L, int nsla
         blocks = 4096;
     if (blocks < 1)
         blocks = 1;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, st, slab_base, L, nslabs, n,
-                       out, perm);
+    // about 1024 blocks in all: slab groups when the vertices alone give fewer
+    int groups = 1;
+    if (blocks < 1024 && nslabs > 1)
+        groups = std::min(nslabs, (1024 + blocks - 1) / blocks);
+    const int per_group = (nslabs + groups - 1) / std::max(groups, 1);
+    groups = per_group > 0 ? (nslabs + per_group - 1) / per_group : 1;
+    if (groups > 1) {
+        const hipError_t e = launch_fill_u64((unsigned long long *)out, (size_t)n, 0ull, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks, std::max(groups, 1)), dim3(256), 0, st,
+                       slab_base, L, nslabs, n, out, perm, std::max(per_group, 1));
     return hipGetLastError();
 }
 
